@@ -1,0 +1,226 @@
+"""Offline GLE fitter: (A_p, C_p) whose stationary <q^2>(omega) follows a
+target f(omega^2) over a spectral window.
+
+TEST INFRASTRUCTURE / INPUT PREPARATION (part of the oracle).  It writes the
+parameter files under ``fth_inputs/gle/``; both the oracle and the HIP library
+read those files as plain input, so the file is the contract and neither
+side re-fits.
+
+Parametrisation (the "delta-like memory kernel" form the paper starts from,
+Sec. I, fitting paragraph):
+    A_p = [[a_pp, a^T], [-a, A]],  A = blockdiag of 2x2 [[g_k, w_k], [-w_k, g_k]]
+    (a trailing 1x1 block [g] when ns is odd),
+with a_pp, g_k > 0.  The symmetric part of A_p is then diag(a_pp, g_k, ...),
+positive definite, so A_p is stable by construction.  The diffusion B_p is
+a lower-triangular matrix with positive diagonal, and C_p follows from the
+Lyapunov relation A_p C_p + C_p A_p^T = B_p B_p^T (Sec. I), which keeps C_p
+positive definite and B_p B_p^T positive semi-definite by construction.
+
+Objective (the three requirements of Sec. II):
+  (1) agreement of g0(lambda) = <q^2>(sqrt(lambda)) with f(lambda) on a
+      log-spaced grid over the window: log residuals, or for targets with an
+      exponentially decaying tail (Fermi) residuals relative to max f where
+      f is not negligible plus a hinge penalty that only asks for
+      g0 < delta * max g0 where f < delta (the paper's threshold delta);
+  (2) stability for the time step: a_pp, the omega -> infinity limit of the
+      friction kernel, kept below omega_max;
+  (3) statistical efficiency: a mild penalty on the slowest relaxation time
+      of each mode measured in units of its period.
+
+Usage:  python -m oracle.fit_gle          (writes the standard files)
+"""
+from __future__ import annotations
+
+import json
+import math
+import os
+import sys
+import time
+
+import numpy as np
+import scipy.optimize
+
+if __package__ in (None, ""):
+    sys.path.insert(0, os.path.dirname(os.path.dirname(os.path.abspath(__file__))))
+    __package__ = "oracle"
+
+from . import check_gle, propagator  # noqa: E402
+from .exact import g0, gh, tau_slowest  # noqa: E402
+
+
+def n_params(ns: int) -> int:
+    d = ns + 1
+    nblk2 = ns // 2
+    return 1 + ns + 2 * nblk2 + (ns % 2) + d * (d + 1) // 2
+
+
+def unpack(theta: np.ndarray, ns: int):
+    d = ns + 1
+    k = 0
+    a_pp = math.exp(theta[k]); k += 1
+    a = theta[k:k + ns]; k += ns
+    A = np.zeros((ns, ns))
+    for b in range(ns // 2):
+        g = math.exp(theta[k]); w = theta[k + 1]; k += 2
+        A[2 * b:2 * b + 2, 2 * b:2 * b + 2] = [[g, w], [-w, g]]
+    if ns % 2:
+        A[ns - 1, ns - 1] = math.exp(theta[k]); k += 1
+    Ap = np.zeros((d, d))
+    Ap[0, 0] = a_pp
+    Ap[0, 1:] = a
+    Ap[1:, 0] = -a
+    Ap[1:, 1:] = A
+    B = np.zeros((d, d))
+    for i in range(d):
+        for j in range(i + 1):
+            B[i, j] = math.exp(theta[k]) if i == j else theta[k]
+            k += 1
+    import scipy.linalg
+    BB = B @ B.T
+    Cp = scipy.linalg.solve_continuous_lyapunov(Ap, BB)
+    Cp = 0.5 * (Cp + Cp.T)
+    return Ap, Cp
+
+
+def make_target(kind: str, **kw):
+    if kind == "invsqrt":
+        return (lambda x: x ** -0.5), None
+    if kind == "fermi":
+        beta, mu = kw["beta"], kw["mu"]
+        return (lambda x: 0.5 * (1.0 - np.tanh(0.5 * beta * (x - mu)))), kw.get("delta", 1e-3)
+    raise ValueError(kind)
+
+
+def residuals(theta, ns, lam, f_lam, delta, w_max, w_tau=0.005, tail=None):
+    try:
+        Ap, Cp = unpack(theta, ns)
+        g = g0(lam, Ap, Cp)
+    except Exception:
+        return np.full(len(lam) + len(lam) + 1, 1e3)
+    if not np.all(np.isfinite(g)) or np.any(g <= 0):
+        return np.full(len(lam) + len(lam) + 1, 1e3)
+    if delta is None:
+        r_fit = np.log(g) - np.log(f_lam)
+    else:
+        fmax = np.max(f_lam)
+        live = f_lam >= delta * fmax
+        r_fit = np.where(live, (g - f_lam) / fmax, 0.0)
+        gmax = np.max(g)
+        over = np.maximum(0.0, np.log(np.maximum(g, 1e-300)) - np.log(delta * gmax))
+        r_fit = r_fit + np.where(live, 0.0, 0.3 * over)
+    tau = tau_slowest(lam, Ap)
+    r_tau = w_tau * np.log(np.maximum(tau * np.sqrt(lam), 1e-12))
+    r_stab = np.array([10.0 * max(0.0, math.log(Ap[0, 0] / w_max))])
+    return np.concatenate([r_fit, r_tau, r_stab])
+
+
+def fit(kind: str, ns: int, lam_lo: float, lam_hi: float, starts: int = 8, seed: int = 0,
+        npts: int = 48, w_tau: float = 0.005, max_nfev: int = 600, **kw):
+    f, delta = make_target(kind, **kw)
+    lam = np.geomspace(lam_lo, lam_hi, npts)
+    if kind == "fermi":  # denser near the step
+        lam = np.unique(np.concatenate([lam, np.linspace(kw["mu"] - 6 / kw["beta"], kw["mu"] + 6 / kw["beta"], 24)]))
+    f_lam = f(lam)
+    w_max = math.sqrt(lam_hi)
+    rng = np.random.default_rng(seed)
+    best = None
+    for s in range(starts):
+        th = np.zeros(n_params(ns))
+        k = 0
+        th[k] = math.log(math.sqrt(lam_lo * lam_hi) * rng.uniform(0.2, 1.0)); k += 1
+        th[k:k + ns] = rng.normal(0, 1.0, ns) * math.sqrt(lam_hi) ** 0.5; k += ns
+        for b in range(ns // 2):
+            if kind == "fermi":
+                # band-pass start: oscillating memory near the step frequency
+                w0 = math.sqrt(kw["mu"])
+                th[k] = math.log(rng.uniform(0.05, 0.5) * w0)
+                th[k + 1] = w0 * rng.uniform(0.7, 1.4)
+            else:
+                th[k] = rng.uniform(math.log(math.sqrt(lam_lo)), math.log(math.sqrt(lam_hi)))
+                th[k + 1] = rng.uniform(0, 2 * math.sqrt(lam_hi))
+            k += 2
+        if ns % 2:
+            th[k] = math.log(math.sqrt(lam_lo * lam_hi)); k += 1
+        d = ns + 1
+        for i in range(d):
+            for j in range(i + 1):
+                th[k] = rng.normal(0, 0.3) if i == j else rng.normal(0, 0.5)
+                k += 1
+        try:
+            res = scipy.optimize.least_squares(residuals, th, args=(ns, lam, f_lam, delta, w_max, w_tau),
+                                               method="trf", max_nfev=max_nfev, x_scale="jac")
+        except Exception:
+            continue
+        cost = float(np.sum(res.fun ** 2))
+        if best is None or cost < best[0]:
+            best = (cost, res.x)
+        print(f"  start {s}: cost {cost:.4e}", flush=True)
+    Ap, Cp = unpack(best[1], ns)
+    check_gle(Ap, Cp)
+    return Ap, Cp, lam, f
+
+
+def report(kind, Ap, Cp, lam_lo, lam_hi, f, h, **kw):
+    lam = np.geomspace(lam_lo, lam_hi, 400)
+    g = g0(lam, Ap, Cp)
+    fl = f(lam)
+    T, S = propagator(Ap, Cp, h)
+    g_h = gh(lam, Ap, Cp, h, T, S)
+    out = {}
+    if kind == "fermi":
+        fmax = float(np.max(fl))
+        live = fl >= kw.get("delta", 1e-3) * fmax
+        out["max_abs_err_rel_to_max"] = float(np.max(np.abs(g - fl)[live]) / fmax)
+        away = np.abs(lam - kw["mu"]) > 5.0 / kw["beta"]
+        out["max_abs_err_rel_to_max_outside_step"] = float(np.max(np.abs(g - fl)[away]) / fmax)
+        out["max_tail_over_delta"] = float(np.max(g[~live]) / (kw.get("delta", 1e-3) * np.max(g))) if np.any(~live) else 0.0
+    else:
+        out["max_rel_err"] = float(np.max(np.abs(g / fl - 1.0)))
+        out["rms_log_err"] = float(np.sqrt(np.mean(np.log(g / fl) ** 2)))
+    out["max_rel_dt_err_gh_vs_g0"] = float(np.max(np.abs(g_h / g - 1.0)))
+    out["max_tau_slowest"] = float(np.max(tau_slowest(lam, Ap)))
+    out["dt_used_for_report"] = h
+    return out
+
+
+def write(path, name, kind, ns, Ap, Cp, lam_lo, lam_hi, rep, **kw):
+    d = {
+        "name": name,
+        "ns": ns,
+        "A_p": Ap.ravel().tolist(),
+        "C_p": Cp.ravel().tolist(),
+        "target": dict(kind=kind, **kw),
+        "estimator": "<q_i q_j>: the fit targets the stationary <q^2>(omega) = f(omega^2)",
+        "window_lambda": [lam_lo, lam_hi],
+        "fit_report": rep,
+        "written_by": "oracle/fit_gle.py",
+    }
+    with open(path, "w") as fh:
+        json.dump(d, fh, indent=1)
+
+
+def main():
+    here = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+    out_dir = os.path.join(here, "fth_inputs", "gle")
+    os.makedirs(out_dir, exist_ok=True)
+    lam_lo, lam_hi = 0.1, 12.1          # spectrum of the 64^3 periodic Laplacian + 0.1
+    h = 0.1 / math.sqrt(lam_hi)
+    jobs = [
+        ("invsqrt_ns4", "invsqrt", 4, {}),
+        ("fermi_b20_ns4", "fermi", 4, {"beta": 20.0, "mu": 6.1, "delta": 1e-2}),
+    ]
+    only = sys.argv[1:]
+    for name, kind, ns, kw in jobs:
+        if only and name not in only:
+            continue
+        t0 = time.time()
+        print(f"fitting {name}", flush=True)
+        opts = dict(starts=16, w_tau=0.03) if kind == "fermi" else {}
+        Ap, Cp, _, f = fit(kind, ns, lam_lo, lam_hi, **opts, **kw)
+        rep = report(kind, Ap, Cp, lam_lo, lam_hi, f, h, **kw)
+        print(f"  {name}: {rep}  ({time.time() - t0:.1f}s)", flush=True)
+        write(os.path.join(out_dir, name + ".json"), name, kind, ns, Ap, Cp, lam_lo, lam_hi, rep, **kw)
+
+
+if __name__ == "__main__":
+    main()

@@ -1,0 +1,116 @@
+"""Pins of the exact stationary responses g0 and g_h used as statistical
+references: closed forms, the paper's scaling relation, independent library
+routes (scipy's Lyapunov solvers, eigh, dense inverse), h -> 0 convergence,
+and the FFT / Lanczos routes against dense eigendecomposition."""
+import numpy as np
+import pytest
+import scipy.linalg
+
+import fth_inputs
+import oracle
+from oracle import exact
+
+
+def gle(ns, seed):
+    rng = np.random.default_rng(seed)
+    d = ns + 1
+    K = rng.normal(size=(d, d))
+    A = (K - K.T) + np.diag(rng.uniform(0.3, 2.0, d))
+    return A, 1.1 * np.eye(d)
+
+
+def test_g0_canonical_limit():
+    """Sec. I: with a white-noise thermostat at temperature kT a mode of
+    frequency omega has <q^2> = kT / omega^2 and <p^2> = kT."""
+    lam = np.geomspace(0.01, 100, 17)
+    for gamma in (0.1, 1.0, 7.0):
+        assert np.allclose(exact.g0(lam, [[gamma]], [[2.5]]), 2.5 / lam, rtol=1e-12)
+        assert np.allclose(exact.g0_p(lam, [[gamma]], [[2.5]]), 2.5, rtol=1e-12)
+
+
+def test_g0_matches_scipy_lyapunov():
+    A, C = gle(4, 3)
+    lam = np.geomspace(0.1, 12, 9)
+    ref = [exact.g0_cov(l, A, C) for l in lam]
+    got = exact.g0_cov_batch(lam, A, C)
+    for r, g in zip(ref, got):
+        assert np.allclose(r, g, rtol=1e-10, atol=1e-12)
+
+
+def test_g0_scaling_relation():
+    """Sec. I scaling: A' = alpha A, C' = gamma C gives
+    <p p^T> = gamma f(M' / alpha^2); for positions <q^2>'(alpha^2 lam) =
+    (gamma / alpha^2) <q^2>(lam)."""
+    A, C = gle(4, 5)
+    lam = np.geomspace(0.1, 12, 11)
+    for alpha, gam in ((2.0, 0.5), (0.3, 3.0)):
+        gp = exact.g0_p(alpha ** 2 * lam, alpha * A, gam * C)
+        assert np.allclose(gp, gam * exact.g0_p(lam, A, C), rtol=1e-10)
+        gq = exact.g0(alpha ** 2 * lam, alpha * A, gam * C)
+        assert np.allclose(gq, gam / alpha ** 2 * exact.g0(lam, A, C), rtol=1e-10)
+
+
+def test_gh_white_noise_closed_form():
+    """Velocity Verlet conserves p^2/2 + omega^2 (1 - h^2 omega^2 / 4) q^2 / 2
+    and the exact OU step preserves p ~ N(0, kT), so the integrated step
+    samples <q^2> = kT / (omega^2 (1 - h^2 omega^2 / 4))."""
+    h = 0.3
+    lam = np.geomspace(0.05, 30.0, 13)
+    for gamma in (0.2, 1.0, 5.0):
+        got = exact.gh(lam, [[gamma]], [[1.7]], h)
+        assert np.allclose(got, 1.7 / (lam * (1 - h * h * lam / 4)), rtol=1e-10)
+
+
+def test_gh_converges_to_g0_second_order():
+    A, C = gle(4, 7)
+    lam = np.array([0.3, 2.0, 9.0])
+    e1 = np.abs(exact.gh(lam, A, C, 0.02) - exact.g0(lam, A, C))
+    e2 = np.abs(exact.gh(lam, A, C, 0.01) - exact.g0(lam, A, C))
+    ratio = e1 / e2
+    assert np.all((ratio > 3.5) & (ratio < 4.5)), ratio
+
+
+def test_gh_matches_long_time_limit_of_finite_cov():
+    A, C = gle(2, 9)
+    h = 0.1
+    T, S = oracle.propagator(A, C, h)
+    for lam in (0.5, 3.0):
+        X = exact.finite_cov(lam, T, S, h, 20000)
+        assert np.allclose(X, exact.gh_cov(lam, T, S, h), rtol=1e-8, atol=1e-12)
+
+
+def test_matrix_function_reduces_to_inverse():
+    m, _ = fth_inputs.haar_spd(12, 3, 0.5, 20.0)
+    assert np.allclose(exact.matrix_function(m, lambda l: 1.0 / l), np.linalg.inv(m), atol=1e-12)
+    assert np.allclose(exact.g0_matrix(m, [[1.0]], [[1.0]]), np.linalg.inv(m), atol=1e-11)
+
+
+@pytest.mark.parametrize("n", [3, 4, 5])
+def test_laplacian_fft_route_matches_eigh(n):
+    A, C = gle(2, 11)
+    h = 0.05
+    csr = fth_inputs.laplacian3d_csr(n, 0.1, dtype=np.float64)
+    M = csr.to_dense()
+    T, S = oracle.propagator(A, C, h)
+    g = lambda l: exact.gh(l, A, C, h, T, S)
+    dense = exact.matrix_function(M, g)
+    K = exact.laplacian_function(n, 0.1, g)
+    i, j = np.meshgrid(np.arange(n ** 3), np.arange(n ** 3), indexing="ij")
+    assert np.allclose(exact.laplacian_element(K, i, j), dense, atol=1e-11)
+
+
+def test_lanczos_quadratic_form_matches_eigh():
+    csr = fth_inputs.banded_spd_csr(300, 4, dtype=np.float64)
+    M = csr.to_dense()
+    g = lambda l: l ** -0.5
+    ref = exact.matrix_function(M, g)
+    for i, j in ((5, 5), (100, 102), (7, 40)):
+        e_i = np.zeros(300); e_i[i] = 1
+        e_j = np.zeros(300); e_j[j] = 1
+        mv = lambda v: M @ v
+        if i == j:
+            val = exact.lanczos_quadratic_form(mv, 300, e_i, g, 120)
+        else:
+            val = 0.25 * (exact.lanczos_quadratic_form(mv, 300, e_i + e_j, g, 120)
+                          - exact.lanczos_quadratic_form(mv, 300, e_i - e_j, g, 120))
+        assert val == pytest.approx(ref[i, j], abs=1e-10)
