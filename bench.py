@@ -1,0 +1,160 @@
+"""Throughput benchmark of the f-thermostat hot path on one MI355X.
+
+A benchmark "step" is one time step of the whole hot path over the
+workload: force -M q, diagonal and pair accumulation, kicks, the exact GLE
+Ornstein-Uhlenbeck update with fresh Philox noise, drift, and block folding
+when due.  The default workload is the 64^3 periodic Laplacian + 0.1
+(N = 262144, CSR, FP32 values) with an ns = 4 GLE (x^-1/2 target), R = 8
+replicas, estimating the diagonal plus 1024 random pairs, 1e4 steps.
+
+Prints one JSON line: throughput in replica*dof*steps/s (inputs resident in
+HBM, timed between stream synchronisations), the step kernel's roofline
+(algorithmic bytes per launch over its HIP-event-measured average duration)
+and, at N = 1 on rank 0, the FP64 CPU oracle timed on a bounded sample of
+the same workload on the host cores.
+"""
+from __future__ import annotations
+
+import argparse
+import json
+import os
+import sys
+import time
+
+import numpy as np
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+import fth_inputs as fi  # noqa: E402
+
+HBM_PEAK_GBS = 8000.0
+
+
+def workload(name: str):
+    """Returns (description dict, matrix CSR, GLE, dt, R, pairs, precision, default steps)."""
+    from paper_1402_2095_amd import fth
+    if name in ("laplacian64", "laplacian64-fp64"):
+        M = fi.laplacian3d_csr(64, 0.1)
+        g = fi.load_gle("invsqrt_ns4")
+        h = fi.dt_rule(fi.laplacian3d_lambda_max(64, 0.1))
+        pairs = fi.random_pairs(M.n, 1024, 2002)
+        prec = fth.FTH_FP64 if name.endswith("fp64") else fth.FTH_FP32
+        desc = {"workload": "3-D periodic 7-point Laplacian 64^3 + 0.1 I (N=262144, CSR)",
+                "gle": "ns=4, x^-1/2 target", "replicas": 8, "estimates": "diagonal + 1024 pairs",
+                "steps_in_config": 10000}
+        return desc, M, g, h, 8, pairs, prec, 10000
+    if name in ("banded1e6", "banded1e6-fp64"):
+        M = fi.banded_spd_csr(1_000_000, 3003)
+        g = fi.load_gle("fermi_b20_ns4")
+        h = fi.dt_rule(fi.gershgorin_max(M))
+        pairs = fi.random_pairs(M.n, 1024, 3004)
+        prec = fth.FTH_FP64 if name.endswith("fp64") else fth.FTH_FP32
+        desc = {"workload": "random banded SPD N=1e6, 7 nonzeros/row (CSR)",
+                "gle": "ns=4, Fermi target", "replicas": 32, "estimates": "diagonal + 1024 pairs",
+                "steps_in_config": 5000}
+        return desc, M, g, h, 32, pairs, prec, 5000
+    raise SystemExit(f"unknown workload {name}")
+
+
+def algorithmic_bytes(M, ns: int, R: int, npairs: int, prec: int) -> float:
+    """Bytes one step must move at minimum: state q (read q_n, write q_{n+1}),
+    p and s_1..s_ns read and written; the CSR arrays once (row_ptr 8 B, col 4
+    B, value per nonzero); the diagonal block accumulator read and written
+    (FP64); each pair's two q rows and its accumulator."""
+    from paper_1402_2095_amd import fth
+    b = 8 if prec == fth.FTH_FP64 else 4
+    n = M.n
+    state = 2 * (ns + 2) * b * n * R
+    csr = (n + 1) * 8 + M.nnz * (4 + b)
+    diag = 16 * n
+    pairs = npairs * (2 * R * b + 16 + 8)
+    return float(state + csr + diag + pairs)
+
+
+def cpu_baseline(M, g, h, R, pairs, budget_s: float):
+    import oracle
+    nthreads = oracle.max_threads()
+    M64 = fi.CSR(M.n, M.row_ptr, M.col, M.val.astype(np.float64))
+    run = oracle.OracleRun(M64, g.A_p, g.C_p, h, R, np.concatenate([pairs, fi.diag_pairs(M.n)]), seed=2)
+    run.run(1)  # warm-up
+    steps = 0
+    t0 = time.perf_counter()
+    while time.perf_counter() - t0 < budget_s and steps < 2000:
+        run.run(1)
+        steps += 1
+    dt = time.perf_counter() - t0
+    return {"value": M.n * R * steps / dt, "unit": "replica*dof*steps/s", "cores": nthreads, "kind": "oracle",
+            "sample": f"full workload (N={M.n}, R={R}, diagonal + {len(pairs)} pairs), {steps} steps after 1 "
+                      f"warm-up step, {dt:.1f} s, FP64, OpenMP over rows"}
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=None)
+    ap.add_argument("--warmup", type=int, default=200)
+    ap.add_argument("--workload", default="laplacian64")
+    ap.add_argument("--steps-per-graph", type=int, default=64)
+    ap.add_argument("--cpu-budget", type=float, default=12.0)
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    args = ap.parse_args()
+    if args.gpus != 1:
+        print("bench.py: this build runs on one GPU only; --gpus must be 1", file=sys.stderr)
+        sys.exit(2)
+
+    import torch
+    from paper_1402_2095_amd import fth
+
+    desc, M, g, h, R, pairs, prec, default_steps = workload(args.workload)
+    steps = args.steps or default_steps
+    print(f"[bench] workload={args.workload} N={M.n} R={R} steps={steps} warmup={args.warmup}", file=sys.stderr,
+          flush=True)
+    torch.cuda.init()
+    stream = torch.cuda.current_stream()
+    sol = fth.Solver(M, g.A_p, g.C_p, h, pairs=pairs, replicas=R, precision=prec, seed=2, acc_diag=True,
+                     steps_per_graph=args.steps_per_graph, block_len=100, hip_stream=stream.cuda_stream)
+    if args.warmup:
+        sol.run(args.warmup)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    sol.run(steps)
+    torch.cuda.synchronize()
+    wall = time.perf_counter() - t0
+    gpu_ms = sol.last_run_ms
+    launches = steps * fth.fth_launches_per_step(sol.ctx)
+    per_launch_s = gpu_ms * 1e-3 / launches
+    abytes = algorithmic_bytes(M, g.ns, R, len(pairs), prec)
+    achieved = abytes / per_launch_s / 1e9
+    est, se, nsamp = sol.read()
+    assert np.all(np.isfinite(est)), "non-finite estimates"
+
+    value = M.n * R * steps / wall
+    out = {
+        "metric": "replica*dof*steps/s",
+        "value": value,
+        "unit": "replica*dof*steps/s",
+        "n_gpus": 1,
+        "steps": steps,
+        "warmup": args.warmup,
+        "ms_per_step": wall * 1e3 / steps,
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "f64" if prec == fth.FTH_FP64 else "f32",
+        "data": "synthetic",
+        "config": dict(desc, precision="fp64" if prec == fth.FTH_FP64 else "fp32 state, fp64 accumulators",
+                       steps_per_graph=args.steps_per_graph, kernel=sol.kernel_name),
+        "roofline": {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
+                     "frac": achieved / HBM_PEAK_GBS, "traffic": None,
+                     "algorithmic_bytes_per_launch": abytes, "avg_launch_us": per_launch_s * 1e6},
+        "cpu_baseline": None,
+    }
+    if not args.no_cpu_baseline:
+        out["cpu_baseline"] = cpu_baseline(M, g, h, R, pairs, args.cpu_budget)
+    sol.close()
+    print(json.dumps(out), flush=True)
+
+
+if __name__ == "__main__":
+    main()

@@ -1,0 +1,215 @@
+/*
+ * fth.h - C ABI of the f-thermostat (FTH) library for AMD Instinct MI355X
+ * (CDNA4, gfx950).
+ *
+ * Method (Nava, Ceriotti, Dryzun, Parrinello, "Evaluating functions of
+ * positive-definite matrices using colored noise thermostats"):
+ * a symmetric positive-definite matrix M is used as the Hessian of the
+ * harmonic potential V(q) = q^T M q / 2 (Sec. I, Eq. for V), every Cartesian
+ * degree of freedom is coupled to an independent copy of a Markovian
+ * colored-noise GLE thermostat (Sec. I, extended-momentum SDE with drift
+ * matrix A_p and free-particle covariance C_p, related to the diffusion by
+ * A_p C_p + C_p A_p^T = B_p B_p^T), and time averages of products of the
+ * dynamical variables give elements of a matrix function (Sec. I, covariance
+ * identity <x_i x_j> = sum_k U_ik g(eps_k) U_jk).  This library estimates
+ * <q_i q_j> = g_h(M)_ij, where g_h(lambda) is the stationary <q^2> of a mode
+ * of frequency sqrt(lambda) under the integrated dynamics; a GLE fitted so
+ * that g_h(lambda) ~ f(lambda) makes these the elements of f(M).
+ *
+ * One time step of size h, for every degree of freedom i and replica r:
+ *   F = -M q_n                       (dense row or CSR row, stored order)
+ *   accumulate q_n products          (selected pairs and/or all diagonals)
+ *   p += (h/2) F
+ *   (p, s_1..s_ns) <- T (p, s) + S xi,  T = exp(-A_p h),
+ *                                       S = chol(C_p - T C_p T^T)
+ *   p += (h/2) F
+ *   q_{n+1} = q_n + h p
+ * (the exact Ornstein-Uhlenbeck step of the GLE between the two half kicks
+ * of velocity Verlet; Sec. I, "modified velocity Verlet").
+ *
+ * Noise xi_j for dof i, replica r, step n, seed K and stream id sigma:
+ * Philox4x32-10 (Salmon et al., SC'11) with key (K mod 2^32, K >> 32) and
+ * counter (i mod 2^32, n mod 2^32, (j << 16) | (r >> 2), sigma); word r & 3
+ * of the block, mapped to u = (2 (x >> 9) + 1) 2^-24, and Box-Muller on the
+ * word pairs (0,1), (2,3): even word sqrt(-2 ln u_even) cos(2 pi u_odd), odd
+ * word the same radius times sin(2 pi u_odd).  Requirements: n < 2^32 dofs,
+ * fewer than 2^32 total steps, R <= 2^18 replicas, ns < 2^16.
+ *
+ * Conventions
+ *  - All pointers passed to fth_create / fth_set_state / fth_read /
+ *    fth_get_* are HOST pointers owned by the caller; inputs are deep-copied
+ *    (uploaded) before the call returns.  The context owns all device memory.
+ *  - Functions return fth_status; nothing throws or aborts across the ABI.
+ *    A message describing the last failure on the calling thread is
+ *    available from fth_last_error().
+ *  - A context is not thread-safe; distinct contexts are independent.
+ *  - Work is enqueued on the context's HIP stream; fth_run returns after the
+ *    stream has drained (so results and errors are final).
+ */
+#ifndef FTH_H
+#define FTH_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef struct fth_ctx fth_ctx;
+
+typedef enum {
+    FTH_OK = 0,
+    FTH_EINVAL = -1,         /* invalid argument (matrix, GLE, dt, pairs, sizes) */
+    FTH_ENOMEM = -2,         /* device or host allocation failed */
+    FTH_EDEVICE = -3,        /* HIP runtime error or no usable gfx950 device */
+    FTH_ESTATE = -4,         /* call not valid in the context's current state */
+    FTH_ENONFINITE = -5,     /* the dynamics produced a non-finite value; the
+                                context is poisoned (M not SPD or h too large) */
+    FTH_EUNSUPPORTED = -6    /* valid request this build does not implement */
+} fth_status;
+
+typedef enum { FTH_DENSE = 0, FTH_CSR = 1 } fth_format;
+
+/* State precision / force form. */
+typedef enum {
+    FTH_FP64 = 0,            /* FP64 state, FP64 force (plain FP64 form) */
+    FTH_FP32 = 1,            /* FP32 state, FP32 force (CSR) */
+    FTH_FP32_BF16X3 = 2      /* FP32 state, dense force as split-BF16x3 on MFMA
+                                with FP32 accumulation (dense only) */
+} fth_precision;
+
+/* The matrix M (Sec. I: the Hessian of the harmonic potential).
+ * FTH_DENSE: dense[n*n] row-major, symmetric.
+ * FTH_CSR:   row_ptr[n+1] (row_ptr[0] == 0, non-decreasing, row_ptr[n] == nnz),
+ *            col[nnz] sorted strictly increasing within each row, 0 <= col < n,
+ *            val[nnz]; the pattern and values must be symmetric and every
+ *            diagonal entry present and positive.
+ * Values are double if value_is_f64 != 0, else float.  In the FP32 forms the
+ * values are used as float; in FTH_FP64 as double. */
+typedef struct {
+    int32_t format;
+    int32_t value_is_f64;
+    int64_t n;
+    const void* dense;
+    int64_t nnz;
+    const int64_t* row_ptr;
+    const int32_t* col;
+    const void* val;
+} fth_matrix;
+
+/* GLE parameters (Sec. I): drift A_p and free-particle covariance C_p,
+ * both (ns+1) x (ns+1) row-major doubles, index 0 the physical momentum.
+ * Requirements: C_p symmetric positive definite; A_p C_p + C_p A_p^T
+ * positive semi-definite; C_p - T C_p T^T positive definite for the
+ * requested dt (checked by Cholesky; failure -> FTH_EINVAL). */
+typedef struct {
+    int32_t ns;
+    const double* A_p;
+    const double* C_p;
+} fth_gle;
+
+typedef struct {
+    uint64_t seed;           /* Philox key */
+    uint32_t stream_id;      /* Philox counter word 3 (distinct per request) */
+    int32_t precision;       /* fth_precision */
+    int64_t burn_in;         /* steps n < burn_in are not accumulated */
+    int64_t block_len;       /* L >= 1: accumulated steps per block average */
+    int32_t acc_diag;        /* != 0: also accumulate all n diagonal elements */
+    int32_t replicas;        /* R, 0: fixed by the first fth_run */
+    void* hip_stream;        /* hipStream_t to enqueue on; NULL: own stream */
+    int32_t steps_per_graph; /* steps captured per hipGraph launch, 0: default */
+    int32_t tune;            /* != 0: autotune the launch shape at first run */
+} fth_options;
+
+/* Fill *opt with defaults: seed 0, stream 0, FTH_FP32, burn_in 0,
+ * block_len 100, acc_diag 0, replicas 0, own stream, default graph length,
+ * no autotuning. */
+void fth_default_options(fth_options* opt);
+
+/* Validate and upload M, compute T and S in FP64 on the host, and upload the
+ * pair list pairs[2*k], pairs[2*k+1] (k < npairs; 0 <= i, j < n; pairs may
+ * be NULL when npairs == 0).  On success *out owns a new context.
+ * Errors: FTH_EINVAL (validation), FTH_ENOMEM, FTH_EDEVICE,
+ * FTH_EUNSUPPORTED (e.g. FTH_FP32_BF16X3 with a CSR matrix). */
+fth_status fth_create(const fth_matrix* M, const fth_gle* gle, double dt,
+                      const int32_t* pairs, int64_t npairs,
+                      const fth_options* opt, fth_ctx** out);
+
+/* Advance the trajectory and the accumulators by nsteps steps over R
+ * replicas (cumulative: continues from the previous call).  The first call
+ * fixes R (replicas == 0 uses opt.replicas); a later call with another
+ * non-zero R returns FTH_ESTATE.  R must be a power of two <= 512 for the
+ * sparse kernels.  Returns FTH_ENONFINITE (and poisons the context) if any
+ * state value became non-finite; FTH_ESTATE on a poisoned context. */
+fth_status fth_run(fth_ctx* ctx, int64_t nsteps, int32_t replicas);
+
+/* Number of estimates: npairs, plus n when acc_diag (pairs first, in input
+ * order, then the diagonal in index order). */
+int64_t fth_num_outputs(const fth_ctx* ctx);
+
+/* Estimates of <q_i q_j> and their standard errors (len >= fth_num_outputs,
+ * else FTH_EINVAL).  mean = (sum of all accumulated samples) / (R n_acc);
+ * stderr from the complete blocks (+inf with fewer than two).  Either output
+ * pointer may be NULL.  *nsamples (if not NULL) receives n_acc, the number of
+ * accumulated steps.  Does not reset anything. */
+fth_status fth_read(fth_ctx* ctx, double* estimates, double* stderr_out,
+                    int64_t len, int64_t* nsamples);
+
+/* Raw accumulators, each of length fth_num_outputs: blk = current partial
+ * block sum, s1 / s2 = sum / sum of squares of completed block sums (sums
+ * over replicas of q_i q_j).  *nblocks = completed blocks, *step = steps
+ * taken so far.  Any pointer may be NULL. */
+fth_status fth_get_accumulators(fth_ctx* ctx, double* blk, double* s1, double* s2,
+                                int64_t* nblocks, int64_t* step);
+
+/* Copy the state to host FP64 arrays: q[n*R], p[n*R] (index i*R + r) and
+ * s[ns*n*R] (index (k*n + i)*R + r).  FTH_ESTATE before R is fixed. */
+fth_status fth_get_state(fth_ctx* ctx, double* q, double* p, double* s);
+
+/* Overwrite the state from host FP64 arrays (same layout; NULL leaves that
+ * part unchanged).  Values are rounded to the state precision. */
+fth_status fth_set_state(fth_ctx* ctx, const double* q, const double* p, const double* s);
+
+/* GPU time in milliseconds of the most recent fth_run, measured with HIP
+ * events on the context's stream around its launches (0 before any run). */
+double fth_last_run_ms(const fth_ctx* ctx);
+
+/* Number of kernel launches per time step of the context's step schedule
+ * (for per-launch timing), and a short name of the step kernel variant in
+ * use (NUL-terminated, at most len bytes written). */
+int32_t fth_launches_per_step(const fth_ctx* ctx);
+fth_status fth_kernel_name(const fth_ctx* ctx, char* name, size_t len);
+
+/* Host-only helpers (no device needed). */
+/* T = exp(-A_p dt) and S = lower Cholesky factor of C_p - T C_p T^T,
+ * (ns+1)^2 row-major doubles.  Errors: FTH_EINVAL. */
+fth_status fth_propagator(const fth_gle* gle, double dt, double* T, double* S);
+
+/* Evaluate the noise stream on the device (validation of the generator):
+ * out[k] = xi_{j[k]} for dof i[k], replica r[k], step n[k], computed in
+ * FTH_FP32 or FTH_FP64 exactly as the step kernels do; if raw != NULL,
+ * raw[4k..4k+3] = the Philox4x32-10 block that holds it.  Host arrays of
+ * length count (raw: 4*count).  Requires j < 2^16, r < 2^18.  Synchronous.
+ * Errors: FTH_EINVAL, FTH_ENOMEM, FTH_EDEVICE. */
+fth_status fth_noise_sample(uint64_t seed, uint32_t stream, int64_t count, const uint32_t* i,
+                            const uint32_t* r, const uint32_t* n, const uint32_t* j,
+                            int32_t precision, double* out, uint32_t* raw);
+
+/* Device bytes a context with these parameters allocates. */
+size_t fth_footprint_bytes(const fth_matrix* M, int32_t ns, int32_t replicas,
+                           int64_t npairs, int32_t acc_diag, int32_t precision);
+
+/* Release the context and its device memory.  NULL is accepted. */
+fth_status fth_destroy(fth_ctx* ctx);
+
+/* Message for the last failure on the calling thread ("" if none). */
+const char* fth_last_error(void);
+
+/* Library version string. */
+const char* fth_version(void);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* FTH_H */

@@ -1,0 +1,636 @@
+// C ABI of the f-thermostat library: validation, per-solve setup (T, S in
+// FP64), device memory, the captured step schedule, and result readout.
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <cmath>
+#include <cstdarg>
+#include <cstdio>
+#include <cstring>
+#include <limits>
+#include <memory>
+#include <string>
+#include <vector>
+
+#include "../../include/fth.h"
+#include "fth_internal.h"
+
+namespace {
+
+thread_local std::string g_last_error;
+
+fth_status fail(fth_status st, const char* fmt, ...) {
+    char buf[512];
+    va_list ap;
+    va_start(ap, fmt);
+    std::vsnprintf(buf, sizeof(buf), fmt, ap);
+    va_end(ap);
+    g_last_error = buf;
+    return st;
+}
+
+#define HIP_OK(expr)                                                                          \
+    do {                                                                                      \
+        hipError_t e_ = (expr);                                                               \
+        if (e_ != hipSuccess)                                                                 \
+            return fail(e_ == hipErrorOutOfMemory ? FTH_ENOMEM : FTH_EDEVICE, "%s: %s", #expr, \
+                        hipGetErrorString(e_));                                               \
+    } while (0)
+
+constexpr int kBlock = 256;
+constexpr int kDefaultGraphSteps = 64;
+
+bool is_pow2(int64_t x) { return x > 0 && (x & (x - 1)) == 0; }
+int ilog2(int64_t x) {
+    int r = 0;
+    while ((int64_t(1) << r) < x) ++r;
+    return r;
+}
+
+}  // namespace
+
+struct fth_ctx {
+    // problem
+    int64_t n = 0;
+    int fmt = FTH_CSR;
+    int prec = FTH_FP32;
+    int ns = 0;
+    double h = 0.0;
+    fth_options opt{};
+    int64_t npairs = 0;
+    int64_t nnz = 0;
+    std::vector<double> T, S;
+    // device buffers
+    std::vector<void*> allocs;
+    int64_t* d_row_ptr = nullptr;
+    int32_t* d_col = nullptr;
+    void* d_val = nullptr;
+    void* d_TS = nullptr;
+    int32_t* d_pairs = nullptr;
+    void* d_q[2] = {nullptr, nullptr};
+    void* d_p = nullptr;
+    void* d_s = nullptr;
+    double* d_acc = nullptr;  // [3][n_out]: blk, s1, s2 (pairs first, then diagonal)
+    int64_t* d_step = nullptr;
+    int32_t* d_flag = nullptr;
+    // schedule
+    int R = 0;
+    int rpt = 0;
+    hipStream_t stream = nullptr;
+    hipEvent_t ev0 = nullptr, ev1 = nullptr;
+    hipGraphExec_t gexec = nullptr;
+    int gK = 0;
+    int64_t step = 0;
+    bool poisoned = false;
+    double last_ms = 0.0;
+    int device = 0;
+
+    ~fth_ctx() {
+        if (gexec) (void)hipGraphExecDestroy(gexec);
+        if (ev0) (void)hipEventDestroy(ev0);
+        if (ev1) (void)hipEventDestroy(ev1);
+        if (stream) (void)hipStreamSynchronize(stream);
+        for (void* p : allocs) (void)hipFree(p);
+        if (stream) (void)hipStreamDestroy(stream);
+    }
+
+    size_t real_bytes() const { return prec == FTH_FP64 ? 8 : 4; }
+    int64_t n_out() const { return npairs + (opt.acc_diag ? n : 0); }
+
+    hipError_t dalloc(void** p, size_t bytes) {
+        *p = nullptr;
+        if (bytes == 0) bytes = 256;
+        hipError_t e = hipMalloc(p, bytes);
+        if (e == hipSuccess) allocs.push_back(*p);
+        return e;
+    }
+};
+
+namespace {
+
+// ------------------------------------------------------------------ checks
+fth_status check_csr(const fth_matrix* M) {
+    const int64_t n = M->n, nnz = M->nnz;
+    if (!M->row_ptr || !M->col || !M->val) return fail(FTH_EINVAL, "CSR arrays must not be NULL");
+    if (M->row_ptr[0] != 0 || M->row_ptr[n] != nnz) return fail(FTH_EINVAL, "row_ptr[0] must be 0 and row_ptr[n] == nnz");
+    auto val = [&](int64_t k) {
+        return M->value_is_f64 ? static_cast<const double*>(M->val)[k] : double(static_cast<const float*>(M->val)[k]);
+    };
+    double vmax = 0.0;
+    for (int64_t i = 0; i < n; ++i) {
+        const int64_t b = M->row_ptr[i], e = M->row_ptr[i + 1];
+        if (e < b) return fail(FTH_EINVAL, "row_ptr decreases at row %lld", (long long)i);
+        bool diag = false;
+        for (int64_t k = b; k < e; ++k) {
+            const int32_t c = M->col[k];
+            if (c < 0 || c >= n) return fail(FTH_EINVAL, "column index out of range in row %lld", (long long)i);
+            if (k > b && c <= M->col[k - 1]) return fail(FTH_EINVAL, "columns not strictly increasing in row %lld", (long long)i);
+            const double v = val(k);
+            if (!std::isfinite(v)) return fail(FTH_EINVAL, "non-finite value in row %lld", (long long)i);
+            vmax = std::max(vmax, std::fabs(v));
+            if (c == i) {
+                if (!(v > 0)) return fail(FTH_EINVAL, "diagonal entry of row %lld is not positive", (long long)i);
+                diag = true;
+            }
+        }
+        if (!diag) return fail(FTH_EINVAL, "missing diagonal entry in row %lld", (long long)i);
+    }
+    const double tol = (M->value_is_f64 ? 1e-12 : 1e-6) * vmax;
+    for (int64_t i = 0; i < n; ++i) {
+        for (int64_t k = M->row_ptr[i]; k < M->row_ptr[i + 1]; ++k) {
+            const int32_t j = M->col[k];
+            if (j == i) continue;
+            const int32_t* b = M->col + M->row_ptr[j];
+            const int32_t* e = M->col + M->row_ptr[j + 1];
+            const int32_t* f = std::lower_bound(b, e, int32_t(i));
+            if (f == e || *f != i) return fail(FTH_EINVAL, "CSR pattern not symmetric at (%lld, %d)", (long long)i, j);
+            if (std::fabs(val(f - M->col) - val(k)) > tol)
+                return fail(FTH_EINVAL, "CSR values not symmetric at (%lld, %d)", (long long)i, j);
+        }
+    }
+    return FTH_OK;
+}
+
+fth_status check_dense(const fth_matrix* M) {
+    const int64_t n = M->n;
+    if (!M->dense) return fail(FTH_EINVAL, "dense pointer must not be NULL");
+    auto at = [&](int64_t i, int64_t j) {
+        return M->value_is_f64 ? static_cast<const double*>(M->dense)[i * n + j]
+                               : double(static_cast<const float*>(M->dense)[i * n + j]);
+    };
+    double vmax = 0.0;
+    for (int64_t i = 0; i < n; ++i)
+        for (int64_t j = 0; j < n; ++j) {
+            const double v = at(i, j);
+            if (!std::isfinite(v)) return fail(FTH_EINVAL, "non-finite matrix entry (%lld, %lld)", (long long)i, (long long)j);
+            vmax = std::max(vmax, std::fabs(v));
+        }
+    const double tol = (M->value_is_f64 ? 1e-12 : 1e-6) * vmax;
+    for (int64_t i = 0; i < n; ++i) {
+        if (!(at(i, i) > 0)) return fail(FTH_EINVAL, "diagonal entry %lld is not positive", (long long)i);
+        for (int64_t j = 0; j < i; ++j)
+            if (std::fabs(at(i, j) - at(j, i)) > tol)
+                return fail(FTH_EINVAL, "dense matrix not symmetric at (%lld, %lld)", (long long)i, (long long)j);
+    }
+    return FTH_OK;
+}
+
+// GLE validity and the exact OU propagator (T = exp(-A_p h), S S^T = C_p - T C_p T^T).
+fth_status make_propagator(const fth_gle* g, double dt, std::vector<double>& T, std::vector<double>& S) {
+    if (!g || !g->A_p || !g->C_p) return fail(FTH_EINVAL, "GLE parameters must not be NULL");
+    if (g->ns < 0 || g->ns > 64) return fail(FTH_EINVAL, "ns must be in [0, 64]");
+    if (!(dt > 0) || !std::isfinite(dt)) return fail(FTH_EINVAL, "dt must be positive and finite");
+    const int d = g->ns + 1;
+    const double* A = g->A_p;
+    const double* C = g->C_p;
+    double cmax = 0.0;
+    for (int i = 0; i < d * d; ++i) {
+        if (!std::isfinite(A[i]) || !std::isfinite(C[i])) return fail(FTH_EINVAL, "non-finite GLE parameter");
+        cmax = std::max(cmax, std::fabs(C[i]));
+    }
+    for (int i = 0; i < d; ++i)
+        for (int j = 0; j < i; ++j)
+            if (std::fabs(C[i * d + j] - C[j * d + i]) > 1e-10 * std::max(1.0, cmax))
+                return fail(FTH_EINVAL, "C_p is not symmetric");
+    std::vector<double> L(d * d), BB(d * d), ev(d);
+    if (!fth::la::cholesky(C, d, L.data(), 0.0)) return fail(FTH_EINVAL, "C_p is not positive definite");
+    double bbmax = 0.0;
+    for (int i = 0; i < d; ++i)
+        for (int j = 0; j < d; ++j) {
+            double v = 0.0;
+            for (int k = 0; k < d; ++k) v += A[i * d + k] * C[k * d + j] + C[i * d + k] * A[j * d + k];
+            BB[i * d + j] = v;
+        }
+    for (int i = 0; i < d; ++i)
+        for (int j = 0; j < i; ++j) BB[i * d + j] = BB[j * d + i] = 0.5 * (BB[i * d + j] + BB[j * d + i]);
+    fth::la::sym_eigvals(BB.data(), d, ev.data());
+    for (double e : ev) bbmax = std::max(bbmax, std::fabs(e));
+    for (double e : ev)
+        if (e < -1e-10 * std::max(1.0, bbmax)) return fail(FTH_EINVAL, "A_p C_p + C_p A_p^T is not positive semi-definite");
+
+    std::vector<double> mA(d * d);
+    for (int i = 0; i < d * d; ++i) mA[i] = -A[i] * dt;
+    T.assign(d * d, 0.0);
+    S.assign(d * d, 0.0);
+    if (!fth::la::expm(mA.data(), d, T.data())) return fail(FTH_EINVAL, "exp(-A_p dt) failed");
+    std::vector<double> TC(d * d), sig(d * d);
+    for (int i = 0; i < d; ++i)
+        for (int j = 0; j < d; ++j) {
+            double v = 0.0;
+            for (int k = 0; k < d; ++k) v += T[i * d + k] * C[k * d + j];
+            TC[i * d + j] = v;
+        }
+    for (int i = 0; i < d; ++i)
+        for (int j = 0; j < d; ++j) {
+            double v = 0.0;
+            for (int k = 0; k < d; ++k) v += TC[i * d + k] * T[j * d + k];
+            sig[i * d + j] = C[i * d + j] - v;
+        }
+    for (int i = 0; i < d; ++i)
+        for (int j = 0; j < i; ++j) sig[i * d + j] = sig[j * d + i] = 0.5 * (sig[i * d + j] + sig[j * d + i]);
+    if (!fth::la::cholesky(sig.data(), d, S.data(), 1e-13))
+        return fail(FTH_EINVAL, "C_p - T C_p T^T is not positive definite for this dt");
+    return FTH_OK;
+}
+
+template <typename Real>
+fth_status upload_converted(fth_ctx* c, void** dst, const void* src, int64_t count, bool src_f64) {
+    std::vector<Real> tmp(size_t(std::max<int64_t>(count, 1)));
+    for (int64_t k = 0; k < count; ++k)
+        tmp[k] = src_f64 ? Real(static_cast<const double*>(src)[k]) : Real(static_cast<const float*>(src)[k]);
+    HIP_OK(c->dalloc(dst, sizeof(Real) * size_t(count)));
+    HIP_OK(hipMemcpy(*dst, tmp.data(), sizeof(Real) * size_t(count), hipMemcpyHostToDevice));
+    return FTH_OK;
+}
+
+template <typename Real>
+fth_status upload_TS(fth_ctx* c) {
+    const int d = c->ns + 1;
+    std::vector<Real> ts(2 * d * d);
+    for (int i = 0; i < d * d; ++i) {
+        ts[i] = Real(c->T[i]);
+        ts[d * d + i] = Real(c->S[i]);
+    }
+    HIP_OK(c->dalloc(&c->d_TS, sizeof(Real) * ts.size()));
+    HIP_OK(hipMemcpy(c->d_TS, ts.data(), sizeof(Real) * ts.size(), hipMemcpyHostToDevice));
+    return FTH_OK;
+}
+
+fth_status ensure_state(fth_ctx* c, int32_t R) {
+    if (c->R != 0) {
+        if (R != 0 && R != c->R) return fail(FTH_ESTATE, "replica count is fixed at %d", c->R);
+        return FTH_OK;
+    }
+    if (R == 0) R = c->opt.replicas;
+    if (R == 0) return fail(FTH_EINVAL, "replica count not given");
+    if (!is_pow2(R) || R > 512) return fail(FTH_EUNSUPPORTED, "R must be a power of two <= 512 (got %d)", R);
+    c->R = R;
+    c->rpt = R >= 4 ? (R > 256 ? 8 : 4) : R;
+    const size_t rb = c->real_bytes();
+    const size_t st = size_t(c->n) * size_t(R) * rb;
+    HIP_OK(c->dalloc(&c->d_q[0], st));
+    HIP_OK(c->dalloc(&c->d_q[1], st));
+    HIP_OK(c->dalloc(&c->d_p, st));
+    HIP_OK(c->dalloc(&c->d_s, st * size_t(std::max(c->ns, 1))));
+    HIP_OK(hipMemsetAsync(c->d_q[0], 0, st, c->stream));
+    HIP_OK(hipMemsetAsync(c->d_q[1], 0, st, c->stream));
+    HIP_OK(hipMemsetAsync(c->d_p, 0, st, c->stream));
+    HIP_OK(hipMemsetAsync(c->d_s, 0, st * size_t(std::max(c->ns, 1)), c->stream));
+    HIP_OK(hipStreamSynchronize(c->stream));
+    return FTH_OK;
+}
+
+template <typename Real>
+fth::CsrStepArgs<Real> csr_args(fth_ctx* c) {
+    fth::CsrStepArgs<Real> a{};
+    a.row_ptr = c->d_row_ptr;
+    a.col = c->d_col;
+    a.val = static_cast<const Real*>(c->d_val);
+    a.q0 = static_cast<Real*>(c->d_q[0]);
+    a.q1 = static_cast<Real*>(c->d_q[1]);
+    a.p = static_cast<Real*>(c->d_p);
+    a.s = static_cast<Real*>(c->d_s);
+    a.TS = static_cast<const Real*>(c->d_TS);
+    a.h = Real(c->h);
+    a.hh = Real(0.5 * c->h);
+    a.N = c->n;
+    a.R = c->R;
+    a.lg_tpr = ilog2(c->R / c->rpt);
+    a.key0 = uint32_t(c->opt.seed);
+    a.key1 = uint32_t(c->opt.seed >> 32);
+    a.stream = c->opt.stream_id;
+    a.step_base = c->d_step;
+    a.burn_in = c->opt.burn_in;
+    a.block_len = c->opt.block_len;
+    const int64_t no = c->n_out();
+    double* blk = c->d_acc;
+    double* s1 = c->d_acc + no;
+    double* s2 = c->d_acc + 2 * no;
+    a.pairs = c->d_pairs;
+    a.npairs = c->npairs;
+    a.pblk = blk;
+    a.ps1 = s1;
+    a.ps2 = s2;
+    if (c->opt.acc_diag) {
+        a.dblk = blk + c->npairs;
+        a.ds1 = s1 + c->npairs;
+        a.ds2 = s2 + c->npairs;
+    }
+    a.flag = c->d_flag;
+    const int per_block = kBlock / (c->R / c->rpt);
+    a.row_tiles = (c->n + per_block - 1) / per_block;
+    a.row_tiles_padded = (a.row_tiles + 7) / 8 * 8;
+    return a;
+}
+
+int64_t pair_tiles(fth_ctx* c) {
+    const int per_block = kBlock / (c->R / c->rpt);
+    return (c->npairs + per_block - 1) / per_block;
+}
+
+// Enqueue one step with in-chunk offset k (global step = *d_step + k).
+fth_status enqueue_step(fth_ctx* c, int k) {
+    int rc;
+    if (c->prec == FTH_FP64) {
+        auto a = csr_args<double>(c);
+        rc = fth::launch_csr_step<double>(a, c->ns, c->rpt, k, kBlock, pair_tiles(c), c->stream);
+    } else {
+        auto a = csr_args<float>(c);
+        rc = fth::launch_csr_step<float>(a, c->ns, c->rpt, k, kBlock, pair_tiles(c), c->stream);
+    }
+    if (rc == -2) return fail(FTH_EUNSUPPORTED, "no kernel instantiated for ns=%d", c->ns);
+    if (rc != 0) return fail(FTH_EDEVICE, "step kernel launch failed (%d): %s", rc, hipGetErrorString(hipGetLastError()));
+    return FTH_OK;
+}
+
+fth_status enqueue_chunk(fth_ctx* c, int K) {
+    for (int k = 0; k < K; ++k) {
+        fth_status st = enqueue_step(c, k);
+        if (st != FTH_OK) return st;
+    }
+    if (fth::launch_advance(c->d_step, K, c->stream) != 0) return fail(FTH_EDEVICE, "advance launch failed");
+    return FTH_OK;
+}
+
+fth_status build_graph(fth_ctx* c, int K) {
+    if (c->gexec) {
+        (void)hipGraphExecDestroy(c->gexec);
+        c->gexec = nullptr;
+    }
+    HIP_OK(hipStreamBeginCapture(c->stream, hipStreamCaptureModeRelaxed));
+    fth_status st = enqueue_chunk(c, K);
+    hipGraph_t g = nullptr;
+    hipError_t e = hipStreamEndCapture(c->stream, &g);
+    if (st != FTH_OK) {
+        if (g) (void)hipGraphDestroy(g);
+        return st;
+    }
+    if (e != hipSuccess) return fail(FTH_EDEVICE, "graph capture failed: %s", hipGetErrorString(e));
+    e = hipGraphInstantiate(&c->gexec, g, nullptr, nullptr, 0);
+    (void)hipGraphDestroy(g);
+    if (e != hipSuccess) return fail(FTH_EDEVICE, "graph instantiate failed: %s", hipGetErrorString(e));
+    c->gK = K;
+    return FTH_OK;
+}
+
+}  // namespace
+
+extern "C" {
+
+const char* fth_last_error(void) { return g_last_error.c_str(); }
+const char* fth_version(void) { return "fth-mi355x 0.1 (gfx950)"; }
+
+void fth_default_options(fth_options* opt) {
+    if (!opt) return;
+    std::memset(opt, 0, sizeof(*opt));
+    opt->precision = FTH_FP32;
+    opt->block_len = 100;
+}
+
+fth_status fth_propagator(const fth_gle* gle, double dt, double* T, double* S) {
+    std::vector<double> t, s;
+    fth_status st = make_propagator(gle, dt, t, s);
+    if (st != FTH_OK) return st;
+    if (T) std::memcpy(T, t.data(), sizeof(double) * t.size());
+    if (S) std::memcpy(S, s.data(), sizeof(double) * s.size());
+    return FTH_OK;
+}
+
+size_t fth_footprint_bytes(const fth_matrix* M, int32_t ns, int32_t R, int64_t npairs, int32_t acc_diag,
+                           int32_t precision) {
+    if (!M) return 0;
+    const size_t rb = precision == FTH_FP64 ? 8 : 4;
+    const size_t n = size_t(M->n);
+    size_t bytes = 0;
+    if (M->format == FTH_CSR)
+        bytes += (n + 1) * 8 + size_t(M->nnz) * (4 + rb);
+    else
+        bytes += n * n * (precision == FTH_FP32_BF16X3 ? 4 : rb);
+    bytes += n * size_t(R) * rb * size_t(3 + std::max(ns, 1));
+    const size_t nout = size_t(npairs) + (acc_diag ? n : 0);
+    bytes += nout * 24 + size_t(npairs) * 8;
+    bytes += 2 * size_t(ns + 1) * size_t(ns + 1) * rb + 64;
+    return bytes;
+}
+
+fth_status fth_create(const fth_matrix* M, const fth_gle* gle, double dt, const int32_t* pairs, int64_t npairs,
+                      const fth_options* opt_in, fth_ctx** out) {
+    g_last_error.clear();
+    if (!out) return fail(FTH_EINVAL, "out must not be NULL");
+    *out = nullptr;
+    if (!M || !gle) return fail(FTH_EINVAL, "M and gle must not be NULL");
+    fth_options opt;
+    fth_default_options(&opt);
+    if (opt_in) opt = *opt_in;
+    if (M->n < 1 || M->n > 0xFFFFFFFFll) return fail(FTH_EINVAL, "n must be in [1, 2^32)");
+    if (M->format != FTH_CSR && M->format != FTH_DENSE) return fail(FTH_EINVAL, "unknown matrix format");
+    if (opt.precision < FTH_FP64 || opt.precision > FTH_FP32_BF16X3) return fail(FTH_EINVAL, "unknown precision");
+    if (opt.block_len < 1) return fail(FTH_EINVAL, "block_len must be >= 1");
+    if (opt.burn_in < 0) return fail(FTH_EINVAL, "burn_in must be >= 0");
+    if (npairs < 0 || (npairs > 0 && !pairs)) return fail(FTH_EINVAL, "invalid pair list");
+    for (int64_t k = 0; k < 2 * npairs; ++k)
+        if (pairs[k] < 0 || pairs[k] >= M->n) return fail(FTH_EINVAL, "pair index out of range at %lld", (long long)k);
+    fth_status st = M->format == FTH_CSR ? check_csr(M) : check_dense(M);
+    if (st != FTH_OK) return st;
+    if (M->format == FTH_DENSE) return fail(FTH_EUNSUPPORTED, "dense matrices are not supported by this build yet");
+    if (opt.precision == FTH_FP32_BF16X3) return fail(FTH_EUNSUPPORTED, "split-BF16x3 applies to dense matrices only");
+    if (gle && (gle->ns > fth::kNsMax)) return fail(FTH_EUNSUPPORTED, "ns > %d not instantiated", fth::kNsMax);
+
+    std::unique_ptr<fth_ctx> c(new fth_ctx());
+    c->n = M->n;
+    c->fmt = M->format;
+    c->prec = opt.precision;
+    c->ns = gle->ns;
+    c->h = dt;
+    c->opt = opt;
+    c->npairs = npairs;
+    c->nnz = M->nnz;
+    st = make_propagator(gle, dt, c->T, c->S);
+    if (st != FTH_OK) return st;
+
+    int ndev = 0;
+    if (hipGetDeviceCount(&ndev) != hipSuccess || ndev < 1) return fail(FTH_EDEVICE, "no HIP device available");
+    HIP_OK(hipGetDevice(&c->device));
+    HIP_OK(hipStreamCreateWithFlags(&c->stream, hipStreamNonBlocking));
+    HIP_OK(hipEventCreate(&c->ev0));
+    HIP_OK(hipEventCreate(&c->ev1));
+
+    // matrix
+    HIP_OK(c->dalloc(reinterpret_cast<void**>(&c->d_row_ptr), sizeof(int64_t) * size_t(M->n + 1)));
+    HIP_OK(hipMemcpy(c->d_row_ptr, M->row_ptr, sizeof(int64_t) * size_t(M->n + 1), hipMemcpyHostToDevice));
+    HIP_OK(c->dalloc(reinterpret_cast<void**>(&c->d_col), sizeof(int32_t) * size_t(M->nnz)));
+    HIP_OK(hipMemcpy(c->d_col, M->col, sizeof(int32_t) * size_t(M->nnz), hipMemcpyHostToDevice));
+    st = c->prec == FTH_FP64 ? upload_converted<double>(c.get(), &c->d_val, M->val, M->nnz, M->value_is_f64)
+                             : upload_converted<float>(c.get(), &c->d_val, M->val, M->nnz, M->value_is_f64);
+    if (st != FTH_OK) return st;
+    st = c->prec == FTH_FP64 ? upload_TS<double>(c.get()) : upload_TS<float>(c.get());
+    if (st != FTH_OK) return st;
+
+    // pairs and accumulators
+    HIP_OK(c->dalloc(reinterpret_cast<void**>(&c->d_pairs), sizeof(int32_t) * size_t(2 * npairs)));
+    if (npairs > 0) HIP_OK(hipMemcpy(c->d_pairs, pairs, sizeof(int32_t) * size_t(2 * npairs), hipMemcpyHostToDevice));
+    const size_t accb = sizeof(double) * size_t(3 * c->n_out());
+    HIP_OK(c->dalloc(reinterpret_cast<void**>(&c->d_acc), accb));
+    HIP_OK(hipMemset(c->d_acc, 0, std::max<size_t>(accb, 8)));
+    HIP_OK(c->dalloc(reinterpret_cast<void**>(&c->d_step), sizeof(int64_t)));
+    HIP_OK(hipMemset(c->d_step, 0, sizeof(int64_t)));
+    HIP_OK(c->dalloc(reinterpret_cast<void**>(&c->d_flag), sizeof(int32_t)));
+    HIP_OK(hipMemset(c->d_flag, 0, sizeof(int32_t)));
+    if (opt.replicas != 0) {
+        st = ensure_state(c.get(), opt.replicas);
+        if (st != FTH_OK) return st;
+    }
+    *out = c.release();
+    return FTH_OK;
+}
+
+fth_status fth_run(fth_ctx* c, int64_t nsteps, int32_t replicas) {
+    g_last_error.clear();
+    if (!c) return fail(FTH_EINVAL, "ctx must not be NULL");
+    if (c->poisoned) return fail(FTH_ESTATE, "context is poisoned by a non-finite state");
+    if (nsteps < 0) return fail(FTH_EINVAL, "nsteps must be >= 0");
+    if (c->step + nsteps >= (int64_t(1) << 32)) return fail(FTH_EINVAL, "total steps must stay below 2^32");
+    fth_status st = ensure_state(c, replicas);
+    if (st != FTH_OK) return st;
+    if (nsteps == 0) return FTH_OK;
+    HIP_OK(hipSetDevice(c->device));
+    if (c->opt.hip_stream) {
+        // order after the caller's stream
+        HIP_OK(hipEventRecord(c->ev0, static_cast<hipStream_t>(c->opt.hip_stream)));
+        HIP_OK(hipStreamWaitEvent(c->stream, c->ev0, 0));
+    }
+    const int K = c->opt.steps_per_graph > 0 ? c->opt.steps_per_graph : kDefaultGraphSteps;
+    HIP_OK(hipEventRecord(c->ev0, c->stream));
+    int64_t left = nsteps;
+    if (left >= K) {
+        if (!c->gexec || c->gK != K) {
+            st = build_graph(c, K);
+            if (st != FTH_OK) return st;
+        }
+        while (left >= K) {
+            HIP_OK(hipGraphLaunch(c->gexec, c->stream));
+            left -= K;
+        }
+    }
+    if (left > 0) {
+        st = enqueue_chunk(c, int(left));
+        if (st != FTH_OK) return st;
+    }
+    HIP_OK(hipEventRecord(c->ev1, c->stream));
+    HIP_OK(hipEventSynchronize(c->ev1));
+    float ms = 0.f;
+    HIP_OK(hipEventElapsedTime(&ms, c->ev0, c->ev1));
+    c->last_ms = ms;
+    c->step += nsteps;
+    int32_t flag = 0;
+    HIP_OK(hipMemcpy(&flag, c->d_flag, sizeof(flag), hipMemcpyDeviceToHost));
+    if (flag) {
+        c->poisoned = true;
+        return fail(FTH_ENONFINITE, "non-finite state after step %lld (M not SPD or dt too large)", (long long)c->step);
+    }
+    return FTH_OK;
+}
+
+int64_t fth_num_outputs(const fth_ctx* c) { return c ? c->n_out() : 0; }
+
+fth_status fth_get_accumulators(fth_ctx* c, double* blk, double* s1, double* s2, int64_t* nblocks, int64_t* step) {
+    if (!c) return fail(FTH_EINVAL, "ctx must not be NULL");
+    const int64_t no = c->n_out();
+    HIP_OK(hipStreamSynchronize(c->stream));
+    double* dst[3] = {blk, s1, s2};
+    for (int k = 0; k < 3; ++k)
+        if (dst[k] && no > 0)
+            HIP_OK(hipMemcpy(dst[k], c->d_acc + k * no, sizeof(double) * size_t(no), hipMemcpyDeviceToHost));
+    const int64_t nacc = std::max<int64_t>(0, c->step - c->opt.burn_in);
+    if (nblocks) *nblocks = nacc / c->opt.block_len;
+    if (step) *step = c->step;
+    return FTH_OK;
+}
+
+fth_status fth_read(fth_ctx* c, double* est, double* se, int64_t len, int64_t* nsamples) {
+    if (!c) return fail(FTH_EINVAL, "ctx must not be NULL");
+    const int64_t no = c->n_out();
+    if (len < no) return fail(FTH_EINVAL, "output length %lld < %lld", (long long)len, (long long)no);
+    std::vector<double> blk(no), s1(no), s2(no);
+    int64_t nb = 0, step = 0;
+    fth_status st = fth_get_accumulators(c, blk.data(), s1.data(), s2.data(), &nb, &step);
+    if (st != FTH_OK) return st;
+    const int64_t nacc = std::max<int64_t>(0, step - c->opt.burn_in);
+    const double R = c->R > 0 ? double(c->R) : 1.0;
+    const double L = double(c->opt.block_len);
+    for (int64_t k = 0; k < no; ++k) {
+        if (est) est[k] = nacc > 0 ? (s1[k] + blk[k]) / (R * double(nacc)) : std::numeric_limits<double>::quiet_NaN();
+        if (se) {
+            if (nb < 2) {
+                se[k] = std::numeric_limits<double>::infinity();
+            } else {
+                const double sc = 1.0 / (R * L);
+                const double sb = s1[k] * sc, sbb = s2[k] * sc * sc;
+                const double var = (sbb - sb * sb / double(nb)) / double(nb - 1);
+                se[k] = std::sqrt(std::max(var, 0.0) / double(nb));
+            }
+        }
+    }
+    if (nsamples) *nsamples = nacc;
+    return FTH_OK;
+}
+
+fth_status fth_get_state(fth_ctx* c, double* q, double* p, double* s) {
+    if (!c) return fail(FTH_EINVAL, "ctx must not be NULL");
+    if (c->R == 0) return fail(FTH_ESTATE, "state not allocated (replica count not fixed)");
+    HIP_OK(hipStreamSynchronize(c->stream));
+    const size_t cnt = size_t(c->n) * size_t(c->R);
+    void* src[3] = {c->d_q[c->step & 1], c->d_p, c->d_s};
+    double* dst[3] = {q, p, s};
+    size_t counts[3] = {cnt, cnt, cnt * size_t(c->ns)};
+    for (int k = 0; k < 3; ++k) {
+        if (!dst[k] || counts[k] == 0) continue;
+        if (c->prec == FTH_FP64) {
+            HIP_OK(hipMemcpy(dst[k], src[k], sizeof(double) * counts[k], hipMemcpyDeviceToHost));
+        } else {
+            std::vector<float> tmp(counts[k]);
+            HIP_OK(hipMemcpy(tmp.data(), src[k], sizeof(float) * counts[k], hipMemcpyDeviceToHost));
+            for (size_t i = 0; i < counts[k]; ++i) dst[k][i] = tmp[i];
+        }
+    }
+    return FTH_OK;
+}
+
+fth_status fth_set_state(fth_ctx* c, const double* q, const double* p, const double* s) {
+    if (!c) return fail(FTH_EINVAL, "ctx must not be NULL");
+    if (c->R == 0) return fail(FTH_ESTATE, "state not allocated (replica count not fixed)");
+    HIP_OK(hipStreamSynchronize(c->stream));
+    const size_t cnt = size_t(c->n) * size_t(c->R);
+    void* dst[3] = {c->d_q[c->step & 1], c->d_p, c->d_s};
+    const double* src[3] = {q, p, s};
+    size_t counts[3] = {cnt, cnt, cnt * size_t(c->ns)};
+    for (int k = 0; k < 3; ++k) {
+        if (!src[k] || counts[k] == 0) continue;
+        if (c->prec == FTH_FP64) {
+            HIP_OK(hipMemcpy(dst[k], src[k], sizeof(double) * counts[k], hipMemcpyHostToDevice));
+        } else {
+            std::vector<float> tmp(counts[k]);
+            for (size_t i = 0; i < counts[k]; ++i) tmp[i] = float(src[k][i]);
+            HIP_OK(hipMemcpy(dst[k], tmp.data(), sizeof(float) * counts[k], hipMemcpyHostToDevice));
+        }
+    }
+    return FTH_OK;
+}
+
+double fth_last_run_ms(const fth_ctx* c) { return c ? c->last_ms : 0.0; }
+
+int32_t fth_launches_per_step(const fth_ctx* c) { return c ? 1 : 0; }
+
+fth_status fth_kernel_name(const fth_ctx* c, char* name, size_t len) {
+    if (!c || !name || len == 0) return fail(FTH_EINVAL, "invalid arguments");
+    std::snprintf(name, len, "csr_step_kernel<%s,NS=%d,RPT=%d>", c->prec == FTH_FP64 ? "double" : "float", c->ns,
+                  c->rpt);
+    return FTH_OK;
+}
+
+fth_status fth_destroy(fth_ctx* c) {
+    delete c;
+    return FTH_OK;
+}
+
+}  // extern "C"

@@ -1,0 +1,113 @@
+"""Host-side checks of the C-ABI library that need no GPU: it loads, it
+exports every function include/fth.h declares, its FP64 propagator matches
+the oracle's, and argument validation rejects malformed inputs before any
+device work."""
+import ctypes
+import os
+import re
+
+import numpy as np
+import pytest
+
+import fth_inputs as fi
+import oracle
+from paper_1402_2095_amd import fth
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+
+
+def header_functions():
+    txt = open(os.path.join(ROOT, "include", "fth.h")).read()
+    txt = re.sub(r"/\*.*?\*/", "", txt, flags=re.S)
+    return sorted(set(re.findall(r"\b(fth_[a-z0-9_]+)\s*\(", txt)))
+
+
+def test_library_exports_every_declared_function():
+    L = fth.lib()
+    names = header_functions()
+    assert len(names) >= 15
+    for name in names:
+        assert hasattr(L, name), name
+    assert set(names) == set(fth.EXPORTS)
+    assert "gfx950" in fth.fth_version()
+
+
+@pytest.mark.parametrize("name,dt", [("invsqrt_ns4", 0.0287), ("fermi_b20_ns4", 0.05)])
+def test_host_propagator_matches_oracle(name, dt):
+    g = fi.load_gle(name)
+    T, S = fth.fth_propagator(g.A_p, g.C_p, dt)
+    To, So = oracle.propagator(g.A_p, g.C_p, dt)
+    assert np.allclose(T, To, rtol=0, atol=1e-14)
+    # S is compared through its backward error: Cholesky factors of an
+    # ill-conditioned C_p - T C_p T^T may differ by cond * eps between
+    # correct implementations, S S^T may not.
+    assert np.allclose(np.triu(S, 1), 0.0)
+    assert np.max(np.abs(S @ S.T - So @ So.T)) <= 1e-13 * np.max(np.abs(g.C_p))
+
+
+def test_host_propagator_large_argument_and_white_noise():
+    # a stiff drift exercises the scaling-and-squaring branch
+    A = np.array([[3.0, 40.0, 0.0], [-40.0, 5.0, 2.0], [0.0, -2.0, 80.0]])
+    C = 1.5 * np.eye(3)
+    T, S = fth.fth_propagator(A, C, 0.2)
+    To, So = oracle.propagator(A, C, 0.2)
+    assert np.allclose(T, To, atol=1e-13)
+    assert np.allclose(S, So, atol=1e-12)
+    T, S = fth.fth_propagator([[0.7]], [[2.0]], 0.1)
+    assert T[0, 0] == pytest.approx(np.exp(-0.07), rel=1e-15)
+    assert S[0, 0] == pytest.approx(np.sqrt(2.0 * (1 - np.exp(-0.14))), rel=1e-14)
+
+
+def test_host_propagator_rejects_invalid_gles():
+    with pytest.raises(fth.FthError) as e:
+        fth.fth_propagator([[1.0]], [[-1.0]], 0.1)
+    assert e.value.status == fth.FTH_EINVAL
+    with pytest.raises(fth.FthError):
+        fth.fth_propagator(np.array([[1.0, 10.0], [0.0, 1.0]]), np.eye(2), 0.1)
+    with pytest.raises(fth.FthError):
+        fth.fth_propagator([[1.0]], [[1.0]], -0.1)
+    with pytest.raises(fth.FthError):
+        fth.fth_propagator([[1.0]], [[1.0]], float("nan"))
+
+
+def _create_status(M, A, C, dt, pairs=None, **opt):
+    try:
+        fth.fth_create(M, A, C, dt, pairs, fth.fth_default_options(**opt))
+    except fth.FthError as e:
+        return e.status, str(e)
+    return fth.FTH_OK, ""
+
+
+def test_validation_before_device():
+    csr = fi.banded_spd_csr(50, 1)
+    A, C = [[1.0]], [[1.0]]
+    bad = fi.CSR(csr.n, csr.row_ptr.copy(), csr.col.copy(), csr.val.copy())
+    bad.val[1] += 0.5  # breaks value symmetry
+    st, msg = _create_status(bad, A, C, 0.05)
+    assert st == fth.FTH_EINVAL and "symmetric" in msg
+    bad = fi.CSR(csr.n, csr.row_ptr.copy(), csr.col.copy(), csr.val.copy())
+    bad.col[0], bad.col[1] = bad.col[1], bad.col[0]
+    st, msg = _create_status(bad, A, C, 0.05)
+    assert st == fth.FTH_EINVAL
+    st, msg = _create_status(csr, A, C, 0.05, pairs=np.array([[0, 50]]))
+    assert st == fth.FTH_EINVAL and "pair" in msg
+    st, msg = _create_status(csr, A, [[-1.0]], 0.05)
+    assert st == fth.FTH_EINVAL
+    st, msg = _create_status(csr, A, C, 0.05, block_len=0)
+    assert st == fth.FTH_EINVAL
+    dense = csr.to_dense()
+    dense[0, 1] += 1.0
+    st, msg = _create_status(dense, A, C, 0.05)
+    assert st == fth.FTH_EINVAL and "symmetric" in msg
+    st, msg = _create_status(csr, A, C, 0.05, precision=fth.FTH_FP32_BF16X3)
+    assert st == fth.FTH_EUNSUPPORTED
+
+
+def test_footprint_accounting():
+    csr = fi.laplacian3d_csr(8)
+    b = fth.fth_footprint_bytes(csr, 4, 8, 10, True, fth.FTH_FP32)
+    n, nnz = csr.n, csr.nnz
+    expect = (n + 1) * 8 + nnz * 8 + n * 8 * 4 * 7 + (10 + n) * 24 + 10 * 8 + 2 * 25 * 4 + 64
+    assert b == expect
+    # the paper's count: M + (3 + S) N + 2 A reals; state bytes dominate and scale with R
+    assert fth.fth_footprint_bytes(csr, 4, 16, 10, True, fth.FTH_FP32) - b == n * 8 * 4 * 7
