@@ -3,9 +3,12 @@
 // GLE momenta NS and the replicas handled per thread RPT.
 //
 // Thread mapping: a row i of M is served by TPR = R / RPT consecutive lanes;
-// lane rq owns replicas [rq*RPT, rq*RPT + RPT).  State is replica-innermost
-// ([N][R]), so the lanes of one row read one contiguous R-vector and every
-// matrix entry is reused R times.  Per thread and step:
+// lane rq owns replicas [rq*RPT, rq*RPT + RPT).  State is replica-innermost:
+// q is [N][R] (ping-pong pair), the thermostat part (p, s_1..s_ns) is
+// interleaved per row as ps[N][ns+1][R], so one row's momenta form a single
+// contiguous (ns+1)*R block: the lanes of a wave stream one region for
+// (p, s) instead of ns+1 separate arrays, and every matrix entry is reused R
+// times.  Per thread and step:
 //   1. gather the CSR row: acc = sum_k val[k] q_n[col[k]]   (stored order)
 //   2. diagonal accumulator: sum over the row's replicas of q_i^2 in FP64,
 //      butterfly-reduced across the TPR lanes, one lane updates the block sum
@@ -43,6 +46,31 @@ __device__ __forceinline__ void store_vec(Real* p, const Vec<Real, RPT>& v) {
     *reinterpret_cast<Vec<Real, RPT>*>(p) = v;
 }
 
+// Streaming (non-temporal) forms for state that is touched once per step:
+// when the state does not fit the 256 MB Infinity Cache, keeping it out of
+// L2/MALL leaves those caches to the gathered neighbour rows.
+template <typename Real, int RPT, bool NT>
+__device__ __forceinline__ Vec<Real, RPT> load_state(const Real* p) {
+    if constexpr (NT) {
+        Vec<Real, RPT> v;
+#pragma unroll
+        for (int m = 0; m < RPT; ++m) v.v[m] = __builtin_nontemporal_load(p + m);
+        return v;
+    } else {
+        return load_vec<Real, RPT>(p);
+    }
+}
+
+template <typename Real, int RPT, bool NT>
+__device__ __forceinline__ void store_state(Real* p, const Vec<Real, RPT>& v) {
+    if constexpr (NT) {
+#pragma unroll
+        for (int m = 0; m < RPT; ++m) __builtin_nontemporal_store(v.v[m], p + m);
+    } else {
+        store_vec<Real, RPT>(p, v);
+    }
+}
+
 __device__ __forceinline__ float fmaR(float a, float b, float c) { return __builtin_fmaf(a, b, c); }
 __device__ __forceinline__ double fmaR(double a, double b, double c) { return __builtin_fma(a, b, c); }
 
@@ -64,7 +92,7 @@ __device__ __forceinline__ double group_sum(double x, int tpr) {
     return x;
 }
 
-template <typename Real, int NS, int RPT>
+template <typename Real, int NS, int RPT, bool NT>
 __global__ __launch_bounds__(256) void csr_step_kernel(const CsrStepArgs<Real> a, const int k) {
     constexpr int D = NS + 1;
     using V = Vec<Real, RPT>;
@@ -103,26 +131,55 @@ __global__ __launch_bounds__(256) void csr_step_kernel(const CsrStepArgs<Real> a
     const int64_t i = t * per_block + slot;
     if (i >= a.N) return;
 
-    // 1. force from the CSR row (F = -acc)
+    // Loads first (own state and the first chunk of the CSR row), then the
+    // noise, which needs no memory and covers the load latency, then the
+    // gather FMAs in stored order.
+    constexpr int G = 8;  // CSR entries gathered per batch
+    const int64_t kb = a.row_ptr[i], ke = a.row_ptr[i + 1];
+    const V qi = load_vec<Real, RPT>(qr + i * R + r0);
+    Real* __restrict__ psrow = a.ps + i * (D * R) + r0;  // p, s_1..s_NS of row i
+    const V pv = load_state<Real, RPT, NT>(psrow);
+    V sv[NS > 0 ? NS : 1];
+#pragma unroll
+    for (int c = 0; c < NS; ++c) sv[c] = load_state<Real, RPT, NT>(psrow + (c + 1) * R);
+
+    int64_t cj[G];
+    Real vj[G];
+#pragma unroll
+    for (int u = 0; u < G; ++u) {
+        const bool in = kb + u < ke;
+        cj[u] = in ? int64_t(a.col[kb + u]) : i;
+        vj[u] = in ? a.val[kb + u] : Real(0);
+    }
+    V qj[G];
+#pragma unroll
+    for (int u = 0; u < G; ++u) qj[u] = load_vec<Real, RPT>(qr + cj[u] * R + r0);
+
+    // normals (components 0..NS) while the loads are in flight
+    Real xi[D][RPT];
+#pragma unroll
+    for (int c = 0; c < D; ++c)
+        normals<Real, RPT>(a.key0, a.key1, a.stream, uint32_t(i), uint32_t(n), uint32_t(c), uint32_t(r0), xi[c]);
+
+    // force: acc = sum_k val[k] q_n[col[k]] (F = -acc), stored order
     Real acc[RPT];
 #pragma unroll
     for (int m = 0; m < RPT; ++m) acc[m] = Real(0);
-    const int64_t kb = a.row_ptr[i], ke = a.row_ptr[i + 1];
-    for (int64_t kk = kb; kk < ke; ++kk) {
+#pragma unroll
+    for (int u = 0; u < G; ++u)
+        if (kb + u < ke) {
+#pragma unroll
+            for (int m = 0; m < RPT; ++m) acc[m] = fmaR(vj[u], qj[u].v[m], acc[m]);
+        }
+    for (int64_t kk = kb + G; kk < ke; ++kk) {  // rows longer than one batch
         const int64_t j = a.col[kk];
         const Real v = a.val[kk];
-        const V qj = load_vec<Real, RPT>(qr + j * R + r0);
+        const V q = load_vec<Real, RPT>(qr + j * R + r0);
 #pragma unroll
-        for (int m = 0; m < RPT; ++m) acc[m] = fmaR(v, qj.v[m], acc[m]);
+        for (int m = 0; m < RPT; ++m) acc[m] = fmaR(v, q.v[m], acc[m]);
     }
 
-    const V qi = load_vec<Real, RPT>(qr + i * R + r0);
-    const V pv = load_vec<Real, RPT>(a.p + i * R + r0);
-    V sv[NS > 0 ? NS : 1];
-#pragma unroll
-    for (int c = 0; c < NS; ++c) sv[c] = load_vec<Real, RPT>(a.s + (int64_t(c) * a.N + i) * R + r0);
-
-    // 2. diagonal accumulator from q_n
+    // diagonal accumulator from q_n
     if (a.dblk != nullptr) {
         double x = 0.0;
 #pragma unroll
@@ -130,12 +187,6 @@ __global__ __launch_bounds__(256) void csr_step_kernel(const CsrStepArgs<Real> a
         x = group_sum(x, tpr);
         if (rq == 0 && acc_on) acc_update(a.dblk, a.ds1, a.ds2, i, x, close);
     }
-
-    // 3. normals
-    Real xi[D][RPT];
-#pragma unroll
-    for (int c = 0; c < D; ++c)
-        normals<Real, RPT>(a.key0, a.key1, a.stream, uint32_t(i), uint32_t(n), uint32_t(c), uint32_t(r0), xi[c]);
 
     // 4. kick, exact OU step, kick, drift
     const Real* T = a.TS;
@@ -167,54 +218,58 @@ __global__ __launch_bounds__(256) void csr_step_kernel(const CsrStepArgs<Real> a
         qn.v[m] = fmaR(a.h, pnew, qi.v[m]);
         ok = ok && __builtin_isfinite(qn.v[m]) && __builtin_isfinite(pnew);
     }
-    store_vec<Real, RPT>(a.p + i * R + r0, pn);
+    store_state<Real, RPT, NT>(psrow, pn);
 #pragma unroll
-    for (int c = 0; c < NS; ++c) store_vec<Real, RPT>(a.s + (int64_t(c) * a.N + i) * R + r0, sn[c]);
-    store_vec<Real, RPT>(qw + i * R + r0, qn);
+    for (int c = 0; c < NS; ++c) store_state<Real, RPT, NT>(psrow + (c + 1) * R, sn[c]);
+    store_state<Real, RPT, NT>(qw + i * R + r0, qn);
     if (!ok) atomicOr(a.flag, 1);
 }
 
-template <typename Real, int NS>
+template <typename Real, int NS, bool NT>
 const void* pick_rpt(int rpt) {
     switch (rpt) {
-        case 1: return reinterpret_cast<const void*>(&csr_step_kernel<Real, NS, 1>);
-        case 2: return reinterpret_cast<const void*>(&csr_step_kernel<Real, NS, 2>);
-        case 4: return reinterpret_cast<const void*>(&csr_step_kernel<Real, NS, 4>);
-        case 8: return reinterpret_cast<const void*>(&csr_step_kernel<Real, NS, 8>);
+        case 1: return reinterpret_cast<const void*>(&csr_step_kernel<Real, NS, 1, NT>);
+        case 2: return reinterpret_cast<const void*>(&csr_step_kernel<Real, NS, 2, NT>);
+        case 4: return reinterpret_cast<const void*>(&csr_step_kernel<Real, NS, 4, NT>);
+        case 8: return reinterpret_cast<const void*>(&csr_step_kernel<Real, NS, 8, NT>);
+        default: return nullptr;
+    }
+}
+
+template <typename Real, bool NT>
+const void* pick_ns(int ns, int rpt) {
+    switch (ns) {
+        case 0: return pick_rpt<Real, 0, NT>(rpt);
+        case 1: return pick_rpt<Real, 1, NT>(rpt);
+        case 2: return pick_rpt<Real, 2, NT>(rpt);
+        case 3: return pick_rpt<Real, 3, NT>(rpt);
+        case 4: return pick_rpt<Real, 4, NT>(rpt);
+        case 5: return pick_rpt<Real, 5, NT>(rpt);
+        case 6: return pick_rpt<Real, 6, NT>(rpt);
+        case 7: return pick_rpt<Real, 7, NT>(rpt);
+        case 8: return pick_rpt<Real, 8, NT>(rpt);
+        case 9: return pick_rpt<Real, 9, NT>(rpt);
+        case 10: return pick_rpt<Real, 10, NT>(rpt);
         default: return nullptr;
     }
 }
 
 template <typename Real>
-const void* pick_csr_kernel(int ns, int rpt) {
-    switch (ns) {
-        case 0: return pick_rpt<Real, 0>(rpt);
-        case 1: return pick_rpt<Real, 1>(rpt);
-        case 2: return pick_rpt<Real, 2>(rpt);
-        case 3: return pick_rpt<Real, 3>(rpt);
-        case 4: return pick_rpt<Real, 4>(rpt);
-        case 5: return pick_rpt<Real, 5>(rpt);
-        case 6: return pick_rpt<Real, 6>(rpt);
-        case 7: return pick_rpt<Real, 7>(rpt);
-        case 8: return pick_rpt<Real, 8>(rpt);
-        case 9: return pick_rpt<Real, 9>(rpt);
-        case 10: return pick_rpt<Real, 10>(rpt);
-        default: return nullptr;
-    }
+const void* pick_csr_kernel(int ns, int rpt, bool nt) {
+    return nt ? pick_ns<Real, true>(ns, rpt) : pick_ns<Real, false>(ns, rpt);
 }
 
 }  // namespace dev
 
 template <typename Real>
-int launch_csr_step_impl(const CsrStepArgs<Real>& a, int ns, int rpt, int k, int block, int64_t pair_tiles,
-                         void* stream) {
-    const void* fn = dev::pick_csr_kernel<Real>(ns, rpt);
+int launch_csr_step_impl(const CsrStepArgs<Real>& a, const CsrLaunch& L, int k, void* stream) {
+    const void* fn = dev::pick_csr_kernel<Real>(L.ns, L.rpt, L.nt);
     if (fn == nullptr) return -2;
-    const int64_t grid = a.row_tiles_padded + pair_tiles;
+    const int64_t grid = a.row_tiles_padded + L.pair_tiles;
     if (grid <= 0) return 0;
     if (grid > 0x7FFFFFFF) return -3;
     void* args[] = {const_cast<CsrStepArgs<Real>*>(&a), &k};
-    hipError_t e = hipLaunchKernel(fn, dim3(unsigned(grid)), dim3(unsigned(block)), args, 0,
+    hipError_t e = hipLaunchKernel(fn, dim3(unsigned(grid)), dim3(unsigned(L.block)), args, 0,
                                    static_cast<hipStream_t>(stream));
     return e == hipSuccess ? 0 : -1;
 }

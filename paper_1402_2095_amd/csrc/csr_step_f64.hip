@@ -3,9 +3,8 @@
 
 namespace fth {
 template <>
-int launch_csr_step<double>(const CsrStepArgs<double>& a, int ns, int rpt, int k, int block,
-                            int64_t pair_tiles, void* stream) {
-    return launch_csr_step_impl<double>(a, ns, rpt, k, block, pair_tiles, stream);
+int launch_csr_step<double>(const CsrStepArgs<double>& a, const CsrLaunch& L, int k, void* stream) {
+    return launch_csr_step_impl<double>(a, L, k, stream);
 }
 
 namespace dev {

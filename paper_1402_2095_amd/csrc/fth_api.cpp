@@ -37,7 +37,6 @@ fth_status fail(fth_status st, const char* fmt, ...) {
                         hipGetErrorString(e_));                                               \
     } while (0)
 
-constexpr int kBlock = 256;
 constexpr int kDefaultGraphSteps = 64;
 
 bool is_pow2(int64_t x) { return x > 0 && (x & (x - 1)) == 0; }
@@ -68,14 +67,15 @@ struct fth_ctx {
     void* d_TS = nullptr;
     int32_t* d_pairs = nullptr;
     void* d_q[2] = {nullptr, nullptr};
-    void* d_p = nullptr;
-    void* d_s = nullptr;
+    void* d_ps = nullptr;  // [n][ns+1][R]: p then s_1..s_ns per row
     double* d_acc = nullptr;  // [3][n_out]: blk, s1, s2 (pairs first, then diagonal)
     int64_t* d_step = nullptr;
     int32_t* d_flag = nullptr;
     // schedule
     int R = 0;
     int rpt = 0;
+    bool nt = false;  // streaming state access (state larger than the Infinity Cache)
+    int block = 256;
     hipStream_t stream = nullptr;
     hipEvent_t ev0 = nullptr, ev1 = nullptr;
     hipGraphExec_t gexec = nullptr;
@@ -268,14 +268,14 @@ fth_status ensure_state(fth_ctx* c, int32_t R) {
     c->rpt = R >= 4 ? (R > 256 ? 8 : 4) : R;
     const size_t rb = c->real_bytes();
     const size_t st = size_t(c->n) * size_t(R) * rb;
+    // State streamed once per step: bypass L2/MALL when it cannot stay resident.
+    c->nt = st * size_t(c->ns + 3) > (size_t(128) << 20);
     HIP_OK(c->dalloc(&c->d_q[0], st));
     HIP_OK(c->dalloc(&c->d_q[1], st));
-    HIP_OK(c->dalloc(&c->d_p, st));
-    HIP_OK(c->dalloc(&c->d_s, st * size_t(std::max(c->ns, 1))));
+    HIP_OK(c->dalloc(&c->d_ps, st * size_t(c->ns + 1)));
     HIP_OK(hipMemsetAsync(c->d_q[0], 0, st, c->stream));
     HIP_OK(hipMemsetAsync(c->d_q[1], 0, st, c->stream));
-    HIP_OK(hipMemsetAsync(c->d_p, 0, st, c->stream));
-    HIP_OK(hipMemsetAsync(c->d_s, 0, st * size_t(std::max(c->ns, 1)), c->stream));
+    HIP_OK(hipMemsetAsync(c->d_ps, 0, st * size_t(c->ns + 1), c->stream));
     HIP_OK(hipStreamSynchronize(c->stream));
     return FTH_OK;
 }
@@ -288,8 +288,7 @@ fth::CsrStepArgs<Real> csr_args(fth_ctx* c) {
     a.val = static_cast<const Real*>(c->d_val);
     a.q0 = static_cast<Real*>(c->d_q[0]);
     a.q1 = static_cast<Real*>(c->d_q[1]);
-    a.p = static_cast<Real*>(c->d_p);
-    a.s = static_cast<Real*>(c->d_s);
+    a.ps = static_cast<Real*>(c->d_ps);
     a.TS = static_cast<const Real*>(c->d_TS);
     a.h = Real(c->h);
     a.hh = Real(0.5 * c->h);
@@ -317,15 +316,15 @@ fth::CsrStepArgs<Real> csr_args(fth_ctx* c) {
         a.ds2 = s2 + c->npairs;
     }
     a.flag = c->d_flag;
-    const int per_block = kBlock / (c->R / c->rpt);
+    const int per_block = c->block / (c->R / c->rpt);
     a.row_tiles = (c->n + per_block - 1) / per_block;
     a.row_tiles_padded = (a.row_tiles + 7) / 8 * 8;
     return a;
 }
 
-int64_t pair_tiles(fth_ctx* c) {
-    const int per_block = kBlock / (c->R / c->rpt);
-    return (c->npairs + per_block - 1) / per_block;
+fth::CsrLaunch csr_launch(fth_ctx* c) {
+    const int per_block = c->block / (c->R / c->rpt);
+    return fth::CsrLaunch{c->ns, c->rpt, c->nt, c->block, (c->npairs + per_block - 1) / per_block};
 }
 
 // Enqueue one step with in-chunk offset k (global step = *d_step + k).
@@ -333,10 +332,10 @@ fth_status enqueue_step(fth_ctx* c, int k) {
     int rc;
     if (c->prec == FTH_FP64) {
         auto a = csr_args<double>(c);
-        rc = fth::launch_csr_step<double>(a, c->ns, c->rpt, k, kBlock, pair_tiles(c), c->stream);
+        rc = fth::launch_csr_step<double>(a, csr_launch(c), k, c->stream);
     } else {
         auto a = csr_args<float>(c);
-        rc = fth::launch_csr_step<float>(a, c->ns, c->rpt, k, kBlock, pair_tiles(c), c->stream);
+        rc = fth::launch_csr_step<float>(a, csr_launch(c), k, c->stream);
     }
     if (rc == -2) return fail(FTH_EUNSUPPORTED, "no kernel instantiated for ns=%d", c->ns);
     if (rc != 0) return fail(FTH_EDEVICE, "step kernel launch failed (%d): %s", rc, hipGetErrorString(hipGetLastError()));
@@ -580,19 +579,25 @@ fth_status fth_get_state(fth_ctx* c, double* q, double* p, double* s) {
     if (c->R == 0) return fail(FTH_ESTATE, "state not allocated (replica count not fixed)");
     HIP_OK(hipStreamSynchronize(c->stream));
     const size_t cnt = size_t(c->n) * size_t(c->R);
-    void* src[3] = {c->d_q[c->step & 1], c->d_p, c->d_s};
-    double* dst[3] = {q, p, s};
-    size_t counts[3] = {cnt, cnt, cnt * size_t(c->ns)};
-    for (int k = 0; k < 3; ++k) {
-        if (!dst[k] || counts[k] == 0) continue;
-        if (c->prec == FTH_FP64) {
-            HIP_OK(hipMemcpy(dst[k], src[k], sizeof(double) * counts[k], hipMemcpyDeviceToHost));
-        } else {
-            std::vector<float> tmp(counts[k]);
-            HIP_OK(hipMemcpy(tmp.data(), src[k], sizeof(float) * counts[k], hipMemcpyDeviceToHost));
-            for (size_t i = 0; i < counts[k]; ++i) dst[k][i] = tmp[i];
-        }
+    const size_t D = size_t(c->ns + 1), R = size_t(c->R);
+    std::vector<double> qh(cnt), psh(cnt * D);
+    if (c->prec == FTH_FP64) {
+        HIP_OK(hipMemcpy(qh.data(), c->d_q[c->step & 1], sizeof(double) * cnt, hipMemcpyDeviceToHost));
+        HIP_OK(hipMemcpy(psh.data(), c->d_ps, sizeof(double) * cnt * D, hipMemcpyDeviceToHost));
+    } else {
+        std::vector<float> tq(cnt), tps(cnt * D);
+        HIP_OK(hipMemcpy(tq.data(), c->d_q[c->step & 1], sizeof(float) * cnt, hipMemcpyDeviceToHost));
+        HIP_OK(hipMemcpy(tps.data(), c->d_ps, sizeof(float) * cnt * D, hipMemcpyDeviceToHost));
+        for (size_t k = 0; k < cnt; ++k) qh[k] = tq[k];
+        for (size_t k = 0; k < cnt * D; ++k) psh[k] = tps[k];
     }
+    if (q) std::memcpy(q, qh.data(), sizeof(double) * cnt);
+    for (size_t i = 0; i < size_t(c->n); ++i)
+        for (size_t r = 0; r < R; ++r) {
+            if (p) p[i * R + r] = psh[(i * D) * R + r];
+            if (s)
+                for (size_t k = 0; k + 1 < D; ++k) s[(k * size_t(c->n) + i) * R + r] = psh[(i * D + k + 1) * R + r];
+        }
     return FTH_OK;
 }
 
@@ -601,18 +606,33 @@ fth_status fth_set_state(fth_ctx* c, const double* q, const double* p, const dou
     if (c->R == 0) return fail(FTH_ESTATE, "state not allocated (replica count not fixed)");
     HIP_OK(hipStreamSynchronize(c->stream));
     const size_t cnt = size_t(c->n) * size_t(c->R);
-    void* dst[3] = {c->d_q[c->step & 1], c->d_p, c->d_s};
-    const double* src[3] = {q, p, s};
-    size_t counts[3] = {cnt, cnt, cnt * size_t(c->ns)};
-    for (int k = 0; k < 3; ++k) {
-        if (!src[k] || counts[k] == 0) continue;
-        if (c->prec == FTH_FP64) {
-            HIP_OK(hipMemcpy(dst[k], src[k], sizeof(double) * counts[k], hipMemcpyHostToDevice));
+    const size_t D = size_t(c->ns + 1), R = size_t(c->R);
+    const bool f64 = c->prec == FTH_FP64;
+    const size_t rb = c->real_bytes();
+    auto put = [&](void* dst, const std::vector<double>& src) -> hipError_t {
+        if (f64) return hipMemcpy(dst, src.data(), sizeof(double) * src.size(), hipMemcpyHostToDevice);
+        std::vector<float> t(src.size());
+        for (size_t k = 0; k < src.size(); ++k) t[k] = float(src[k]);
+        return hipMemcpy(dst, t.data(), sizeof(float) * t.size(), hipMemcpyHostToDevice);
+    };
+    if (q) HIP_OK(put(c->d_q[c->step & 1], std::vector<double>(q, q + cnt)));
+    if (p || s) {
+        // read-modify-write of the interleaved (p, s) block
+        std::vector<double> psh(cnt * D);
+        if (f64) {
+            HIP_OK(hipMemcpy(psh.data(), c->d_ps, sizeof(double) * cnt * D, hipMemcpyDeviceToHost));
         } else {
-            std::vector<float> tmp(counts[k]);
-            for (size_t i = 0; i < counts[k]; ++i) tmp[i] = float(src[k][i]);
-            HIP_OK(hipMemcpy(dst[k], tmp.data(), sizeof(float) * counts[k], hipMemcpyHostToDevice));
+            std::vector<float> t(cnt * D);
+            HIP_OK(hipMemcpy(t.data(), c->d_ps, rb * cnt * D, hipMemcpyDeviceToHost));
+            for (size_t k = 0; k < cnt * D; ++k) psh[k] = t[k];
         }
+        for (size_t i = 0; i < size_t(c->n); ++i)
+            for (size_t r = 0; r < R; ++r) {
+                if (p) psh[(i * D) * R + r] = p[i * R + r];
+                if (s)
+                    for (size_t k = 0; k + 1 < D; ++k) psh[(i * D + k + 1) * R + r] = s[(k * size_t(c->n) + i) * R + r];
+            }
+        HIP_OK(put(c->d_ps, psh));
     }
     return FTH_OK;
 }
@@ -623,8 +643,8 @@ int32_t fth_launches_per_step(const fth_ctx* c) { return c ? 1 : 0; }
 
 fth_status fth_kernel_name(const fth_ctx* c, char* name, size_t len) {
     if (!c || !name || len == 0) return fail(FTH_EINVAL, "invalid arguments");
-    std::snprintf(name, len, "csr_step_kernel<%s,NS=%d,RPT=%d>", c->prec == FTH_FP64 ? "double" : "float", c->ns,
-                  c->rpt);
+    std::snprintf(name, len, "csr_step_kernel<%s,NS=%d,RPT=%d,NT=%d>", c->prec == FTH_FP64 ? "double" : "float",
+                  c->ns, c->rpt, int(c->nt));
     return FTH_OK;
 }
 

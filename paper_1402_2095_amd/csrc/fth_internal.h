@@ -17,11 +17,10 @@ struct CsrStepArgs {
     const int64_t* row_ptr;
     const int32_t* col;
     const Real* val;
-    // state: q ping-pong [N][R], p [N][R], s [ns][N][R]
+    // state: q ping-pong [N][R]; p and s interleaved per row, ps[N][ns+1][R]
     Real* q0;
     Real* q1;
-    Real* p;
-    Real* s;
+    Real* ps;
     // propagator T then S, each (ns+1)^2 row-major, state precision
     const Real* TS;
     Real h;
@@ -50,10 +49,18 @@ struct CsrStepArgs {
     int64_t row_tiles_padded;  // rounded up to a multiple of 8 (XCD remap)
 };
 
+// Launch shape of the sparse step.
+struct CsrLaunch {
+    int ns;              // extra GLE momenta (template)
+    int rpt;             // replicas per thread (template: 1, 2, 4, 8)
+    bool nt;             // streaming (non-temporal) state loads/stores (template)
+    int block;           // threads per workgroup
+    int64_t pair_tiles;  // extra workgroups for the selected pairs
+};
+
 // Launch wrappers (defined in the .hip files).
 template <typename Real>
-int launch_csr_step(const CsrStepArgs<Real>& a, int ns, int rpt, int k, int block,
-                    int64_t pair_tiles, void* stream);
+int launch_csr_step(const CsrStepArgs<Real>& a, const CsrLaunch& L, int k, void* stream);
 
 int launch_advance(int64_t* step_base, int64_t k, void* stream);
 
