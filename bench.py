@@ -54,7 +54,35 @@ def workload(name: str):
                 "gle": "ns=4, Fermi target", "replicas": 32, "estimates": "diagonal + 1024 pairs",
                 "steps_in_config": 5000}
         return desc, M, g, h, 32, pairs, prec, 5000
+    if name in ("dense16384", "dense16384-fp64"):
+        n = 16384
+        M = fi.dense_ggt(n, 4004)
+        g = fi.load_gle("invsqrt_ns4")
+        h = fi.dt_rule(fi.power_lambda_max(M.astype(np.float64), iters=30))
+        pairs = fi.random_pairs(n, 1024, 4005)
+        prec = fth.FTH_FP64 if name.endswith("fp64") else fth.FTH_FP32_BF16X3
+        desc = {"workload": "dense SPD N=16384, M = G G^T / N + 0.1 I (FP32 values)",
+                "gle": "ns=4, x^-1/2 target", "replicas": 128, "estimates": "diagonal + 1024 pairs",
+                "steps_in_config": 2000}
+        return desc, M, g, h, 128, pairs, prec, 2000
     raise SystemExit(f"unknown workload {name}")
+
+
+def dense_roofline(M, ns: int, R: int, npairs: int, prec: int, per_step_s: float):
+    """Dense step = GEMM + epilogue.  Bytes: M once (split form: hi + lo
+    bf16 = 4 B per entry; FP64: 8 B), the state as in the sparse step, the
+    split-K partials written and read back.  Flops: 2 N^2 R (algorithmic;
+    the split form issues three bf16 products)."""
+    from paper_1402_2095_amd import fth
+    n = M.shape[0]
+    P = (n + 255) // 256 * 256
+    ks = 8 if P >= 2048 else P // 256
+    b = 8 if prec == fth.FTH_FP64 else 4
+    mbytes = P * P * (8 if prec == fth.FTH_FP64 else 4)
+    state = 2 * (ns + 2) * b * n * R + 16 * n + npairs * (2 * R * b + 24)
+    part = 2 * ks * P * R * b
+    flops = 2.0 * n * n * R
+    return float(mbytes + state + part), flops
 
 
 def algorithmic_bytes(M, ns: int, R: int, npairs: int, prec: int) -> float:
@@ -75,8 +103,13 @@ def algorithmic_bytes(M, ns: int, R: int, npairs: int, prec: int) -> float:
 def cpu_baseline(M, g, h, R, pairs, budget_s: float):
     import oracle
     nthreads = oracle.max_threads()
-    M64 = fi.CSR(M.n, M.row_ptr, M.col, M.val.astype(np.float64))
-    run = oracle.OracleRun(M64, g.A_p, g.C_p, h, R, np.concatenate([pairs, fi.diag_pairs(M.n)]), seed=2)
+    if isinstance(M, np.ndarray):
+        M64 = M.astype(np.float64)
+        n = M.shape[0]
+    else:
+        M64 = fi.CSR(M.n, M.row_ptr, M.col, M.val.astype(np.float64))
+        n = M.n
+    run = oracle.OracleRun(M64, g.A_p, g.C_p, h, R, np.concatenate([pairs, fi.diag_pairs(n)]), seed=2)
     run.run(1)  # warm-up
     steps = 0
     t0 = time.perf_counter()
@@ -84,8 +117,8 @@ def cpu_baseline(M, g, h, R, pairs, budget_s: float):
         run.run(1)
         steps += 1
     dt = time.perf_counter() - t0
-    return {"value": M.n * R * steps / dt, "unit": "replica*dof*steps/s", "cores": nthreads, "kind": "oracle",
-            "sample": f"full workload (N={M.n}, R={R}, diagonal + {len(pairs)} pairs), {steps} steps after 1 "
+    return {"value": n * R * steps / dt, "unit": "replica*dof*steps/s", "cores": nthreads, "kind": "oracle",
+            "sample": f"full workload (N={n}, R={R}, diagonal + {len(pairs)} pairs), {steps} steps after 1 "
                       f"warm-up step, {dt:.1f} s, FP64, OpenMP over rows"}
 
 
@@ -122,8 +155,7 @@ def main():
 
     desc, M, g, h, R, pairs, prec, default_steps = workload(args.workload)
     steps = args.steps or default_steps
-    print(f"[bench] workload={args.workload} N={M.n} R={R} steps={steps} warmup={args.warmup}", file=sys.stderr,
-          flush=True)
+    print(f"[bench] workload={args.workload} R={R} steps={steps} warmup={args.warmup}", file=sys.stderr, flush=True)
     torch.cuda.init()
     stream = torch.cuda.current_stream()
     sol = fth.Solver(M, g.A_p, g.C_p, h, pairs=pairs, replicas=R, precision=prec, seed=2, acc_diag=True,
@@ -138,12 +170,19 @@ def main():
     gpu_ms = sol.last_run_ms
     launches = steps * fth.fth_launches_per_step(sol.ctx)
     per_launch_s = gpu_ms * 1e-3 / launches
-    abytes = algorithmic_bytes(M, g.ns, R, len(pairs), prec)
+    dense = isinstance(M, np.ndarray)
+    if dense:
+        # both launches of a step are timed together: the step is the unit
+        per_launch_s = gpu_ms * 1e-3 / steps
+        abytes, flops = dense_roofline(M, g.ns, R, len(pairs), prec, per_launch_s)
+    else:
+        abytes = algorithmic_bytes(M, g.ns, R, len(pairs), prec)
     achieved = abytes / per_launch_s / 1e9
     est, se, nsamp = sol.read()
     assert np.all(np.isfinite(est)), "non-finite estimates"
 
-    value = M.n * R * steps / wall
+    n = M.shape[0] if dense else M.n
+    value = n * R * steps / wall
     out = {
         "metric": "replica*dof*steps/s",
         "value": value,
@@ -164,6 +203,12 @@ def main():
                      "algorithmic_bytes_per_launch": abytes, "avg_launch_us": per_launch_s * 1e6},
         "cpu_baseline": None,
     }
+    if dense:
+        mfma_peak = 78.6 if prec == fth.FTH_FP64 else 2500.0
+        tf = flops * (3 if prec == fth.FTH_FP32_BF16X3 else 1) / per_launch_s / 1e12
+        out["roofline"]["mfma"] = {"issued_tflops": tf, "peak_tflops": mfma_peak, "frac": tf / mfma_peak,
+                                   "algorithmic_tflops": flops / per_launch_s / 1e12}
+        out["roofline"]["note"] = "one unit = one step (GEMM + epilogue launches)"
     if not args.no_cpu_baseline:
         out["cpu_baseline"] = cpu_baseline(M, g, h, R, pairs, args.cpu_budget)
     sol.close()

@@ -171,6 +171,13 @@ fth_status fth_get_state(fth_ctx* ctx, double* q, double* p, double* s);
  * part unchanged).  Values are rounded to the state precision. */
 fth_status fth_set_state(fth_ctx* ctx, const double* q, const double* p, const double* s);
 
+/* Force check for dense contexts: F = -M q for a host state q[n*R] (index
+ * i*R + r, values rounded to the state precision), computed with the same
+ * device GEMM and partial-sum order as a time step, on scratch buffers (the
+ * trajectory is not touched); F[n*R] receives the result as double.
+ * FTH_ESTATE before R is fixed; FTH_EUNSUPPORTED for CSR contexts. */
+fth_status fth_force(fth_ctx* ctx, const double* q, double* F);
+
 /* GPU time in milliseconds of the most recent fth_run, measured with HIP
  * events on the context's stream around its launches (0 before any run). */
 double fth_last_run_ms(const fth_ctx* ctx);

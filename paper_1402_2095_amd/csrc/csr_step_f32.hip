@@ -3,7 +3,7 @@
 
 namespace fth {
 template <>
-int launch_csr_step<float>(const CsrStepArgs<float>& a, const CsrLaunch& L, int k, void* stream) {
+int launch_csr_step<float>(const StepArgs<float>& a, const StepLaunch& L, int k, void* stream) {
     return launch_csr_step_impl<float>(a, L, k, stream);
 }
 }  // namespace fth

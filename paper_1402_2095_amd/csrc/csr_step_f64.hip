@@ -3,7 +3,7 @@
 
 namespace fth {
 template <>
-int launch_csr_step<double>(const CsrStepArgs<double>& a, const CsrLaunch& L, int k, void* stream) {
+int launch_csr_step<double>(const StepArgs<double>& a, const StepLaunch& L, int k, void* stream) {
     return launch_csr_step_impl<double>(a, L, k, stream);
 }
 

@@ -66,6 +66,14 @@ struct fth_ctx {
     void* d_val = nullptr;
     void* d_TS = nullptr;
     int32_t* d_pairs = nullptr;
+    // dense: M padded to rows_pad x rows_pad (bf16 hi/lo, or double), split-K partials, bf16 q split
+    int64_t rows_pad = 0;
+    int ksplit = 1;
+    void* d_m_hi = nullptr;
+    void* d_m_lo = nullptr;
+    void* d_part = nullptr;
+    uint16_t* d_qt = nullptr;
+    bool qt_dirty = true;
     void* d_q[2] = {nullptr, nullptr};
     void* d_ps = nullptr;  // [n][ns+1][R]: p then s_1..s_ns per row
     double* d_acc = nullptr;  // [3][n_out]: blk, s1, s2 (pairs first, then diagonal)
@@ -95,6 +103,8 @@ struct fth_ctx {
     }
 
     size_t real_bytes() const { return prec == FTH_FP64 ? 8 : 4; }
+    bool dense() const { return fmt == FTH_DENSE; }
+    int64_t q_rows() const { return dense() ? rows_pad : n; }
     int64_t n_out() const { return npairs + (opt.acc_diag ? n : 0); }
 
     hipError_t dalloc(void** p, size_t bytes) {
@@ -256,6 +266,55 @@ fth_status upload_TS(fth_ctx* c) {
     return FTH_OK;
 }
 
+// Dense M padded to rows_pad x rows_pad with zeros (rows_pad a multiple of
+// 256): bf16 hi/lo split on the device for the split form, FP64 as is.
+fth_status upload_dense(fth_ctx* c, const fth_matrix* M) {
+    const int64_t n = M->n;
+    c->rows_pad = (n + 255) / 256 * 256;
+    const int64_t P = c->rows_pad;
+    c->ksplit = P >= 2048 ? 8 : int(P / 256);
+    const size_t cnt = size_t(P) * size_t(P);
+    if (c->prec == FTH_FP64) {
+        HIP_OK(c->dalloc(&c->d_m_hi, cnt * sizeof(double)));
+        HIP_OK(hipMemset(c->d_m_hi, 0, cnt * sizeof(double)));
+        if (M->value_is_f64) {
+            HIP_OK(hipMemcpy2D(c->d_m_hi, size_t(P) * 8, M->dense, size_t(n) * 8, size_t(n) * 8, size_t(n),
+                               hipMemcpyHostToDevice));
+        } else {
+            std::vector<double> row(n);
+            const float* src = static_cast<const float*>(M->dense);
+            for (int64_t i = 0; i < n; ++i) {
+                for (int64_t j = 0; j < n; ++j) row[j] = src[i * n + j];
+                HIP_OK(hipMemcpy(static_cast<double*>(c->d_m_hi) + i * P, row.data(), size_t(n) * 8,
+                                 hipMemcpyHostToDevice));
+            }
+        }
+        return FTH_OK;
+    }
+    float* tmp = nullptr;
+    HIP_OK(hipMalloc(&tmp, cnt * sizeof(float)));
+    std::unique_ptr<float, hipError_t (*)(void*)> guard(tmp, hipFree);
+    HIP_OK(hipMemset(tmp, 0, cnt * sizeof(float)));
+    if (M->value_is_f64) {
+        std::vector<float> row(n);
+        const double* src = static_cast<const double*>(M->dense);
+        for (int64_t i = 0; i < n; ++i) {
+            for (int64_t j = 0; j < n; ++j) row[j] = float(src[i * n + j]);
+            HIP_OK(hipMemcpy(tmp + i * P, row.data(), size_t(n) * 4, hipMemcpyHostToDevice));
+        }
+    } else {
+        HIP_OK(hipMemcpy2D(tmp, size_t(P) * 4, M->dense, size_t(n) * 4, size_t(n) * 4, size_t(n),
+                           hipMemcpyHostToDevice));
+    }
+    HIP_OK(c->dalloc(&c->d_m_hi, cnt * sizeof(uint16_t)));
+    HIP_OK(c->dalloc(&c->d_m_lo, cnt * sizeof(uint16_t)));
+    if (fth::launch_split_bf16(tmp, static_cast<uint16_t*>(c->d_m_hi), static_cast<uint16_t*>(c->d_m_lo),
+                               int64_t(cnt), c->stream) != 0)
+        return fail(FTH_EDEVICE, "bf16 split launch failed");
+    HIP_OK(hipStreamSynchronize(c->stream));
+    return FTH_OK;
+}
+
 fth_status ensure_state(fth_ctx* c, int32_t R) {
     if (c->R != 0) {
         if (R != 0 && R != c->R) return fail(FTH_ESTATE, "replica count is fixed at %d", c->R);
@@ -263,29 +322,50 @@ fth_status ensure_state(fth_ctx* c, int32_t R) {
     }
     if (R == 0) R = c->opt.replicas;
     if (R == 0) return fail(FTH_EINVAL, "replica count not given");
-    if (!is_pow2(R) || R > 512) return fail(FTH_EUNSUPPORTED, "R must be a power of two <= 512 (got %d)", R);
+    if (c->dense()) {
+        if (R != 16 && R != 32 && R != 64 && R != 128)
+            return fail(FTH_EUNSUPPORTED, "dense matrices need R in {16, 32, 64, 128} (got %d)", R);
+    } else if (!is_pow2(R) || R > 512) {
+        return fail(FTH_EUNSUPPORTED, "R must be a power of two <= 512 (got %d)", R);
+    }
     c->R = R;
     c->rpt = R >= 4 ? (R > 256 ? 8 : 4) : R;
     const size_t rb = c->real_bytes();
+    const size_t qst = size_t(c->q_rows()) * size_t(R) * rb;
     const size_t st = size_t(c->n) * size_t(R) * rb;
     // State streamed once per step: bypass L2/MALL when it cannot stay resident.
     c->nt = st * size_t(c->ns + 3) > (size_t(128) << 20);
-    HIP_OK(c->dalloc(&c->d_q[0], st));
-    HIP_OK(c->dalloc(&c->d_q[1], st));
+    HIP_OK(c->dalloc(&c->d_q[0], qst));
+    HIP_OK(c->dalloc(&c->d_q[1], qst));
     HIP_OK(c->dalloc(&c->d_ps, st * size_t(c->ns + 1)));
-    HIP_OK(hipMemsetAsync(c->d_q[0], 0, st, c->stream));
-    HIP_OK(hipMemsetAsync(c->d_q[1], 0, st, c->stream));
+    HIP_OK(hipMemsetAsync(c->d_q[0], 0, qst, c->stream));
+    HIP_OK(hipMemsetAsync(c->d_q[1], 0, qst, c->stream));
     HIP_OK(hipMemsetAsync(c->d_ps, 0, st * size_t(c->ns + 1), c->stream));
+    if (c->dense()) {
+        const size_t pb = size_t(c->ksplit) * size_t(c->rows_pad) * size_t(R) * rb;
+        HIP_OK(c->dalloc(&c->d_part, pb));
+        HIP_OK(hipMemsetAsync(c->d_part, 0, pb, c->stream));
+        if (c->prec == FTH_FP32_BF16X3) {
+            const size_t qtb = size_t(c->rows_pad) * size_t(R) * 2 * sizeof(uint16_t);
+            HIP_OK(c->dalloc(reinterpret_cast<void**>(&c->d_qt), qtb));
+            HIP_OK(hipMemsetAsync(c->d_qt, 0, qtb, c->stream));
+            c->qt_dirty = true;
+        }
+    }
     HIP_OK(hipStreamSynchronize(c->stream));
     return FTH_OK;
 }
 
 template <typename Real>
-fth::CsrStepArgs<Real> csr_args(fth_ctx* c) {
-    fth::CsrStepArgs<Real> a{};
+fth::StepArgs<Real> step_args(fth_ctx* c) {
+    fth::StepArgs<Real> a{};
     a.row_ptr = c->d_row_ptr;
     a.col = c->d_col;
     a.val = static_cast<const Real*>(c->d_val);
+    a.part = static_cast<const Real*>(c->d_part);
+    a.ksplit = c->ksplit;
+    a.rows_pad = c->rows_pad;
+    a.qt = c->d_qt;
     a.q0 = static_cast<Real*>(c->d_q[0]);
     a.q1 = static_cast<Real*>(c->d_q[1]);
     a.ps = static_cast<Real*>(c->d_ps);
@@ -322,20 +402,43 @@ fth::CsrStepArgs<Real> csr_args(fth_ctx* c) {
     return a;
 }
 
-fth::CsrLaunch csr_launch(fth_ctx* c) {
+fth::StepLaunch step_launch(fth_ctx* c) {
     const int per_block = c->block / (c->R / c->rpt);
-    return fth::CsrLaunch{c->ns, c->rpt, c->nt, c->block, (c->npairs + per_block - 1) / per_block};
+    return fth::StepLaunch{c->ns, c->rpt, c->nt, c->block, (c->npairs + per_block - 1) / per_block};
+}
+
+fth::DenseGemmArgs gemm_args(fth_ctx* c, int k) {
+    fth::DenseGemmArgs g{};
+    g.m_hi = c->d_m_hi;
+    g.m_lo = c->d_m_lo;
+    g.qt = c->d_qt;
+    g.q0 = c->d_q[0];
+    g.q1 = c->d_q[1];
+    g.step_base = c->d_step;
+    g.k = k;
+    g.part = c->d_part;
+    g.rows_pad = c->rows_pad;
+    g.R = c->R;
+    g.ksplit = c->ksplit;
+    g.kslice = c->rows_pad / c->ksplit;
+    return g;
 }
 
 // Enqueue one step with in-chunk offset k (global step = *d_step + k).
 fth_status enqueue_step(fth_ctx* c, int k) {
     int rc;
-    if (c->prec == FTH_FP64) {
-        auto a = csr_args<double>(c);
-        rc = fth::launch_csr_step<double>(a, csr_launch(c), k, c->stream);
+    if (c->dense()) {
+        const fth::DenseGemmArgs g = gemm_args(c, k);
+        rc = c->prec == FTH_FP64 ? fth::launch_gemm_f64(g, c->stream) : fth::launch_gemm_bf16x3(g, c->stream);
+        if (rc != 0) return fail(FTH_EDEVICE, "dense GEMM launch failed (%d)", rc);
+        if (c->prec == FTH_FP64)
+            rc = fth::launch_dense_epilogue<double>(step_args<double>(c), step_launch(c), k, c->stream);
+        else
+            rc = fth::launch_dense_epilogue<float>(step_args<float>(c), step_launch(c), k, c->stream);
+    } else if (c->prec == FTH_FP64) {
+        rc = fth::launch_csr_step<double>(step_args<double>(c), step_launch(c), k, c->stream);
     } else {
-        auto a = csr_args<float>(c);
-        rc = fth::launch_csr_step<float>(a, csr_launch(c), k, c->stream);
+        rc = fth::launch_csr_step<float>(step_args<float>(c), step_launch(c), k, c->stream);
     }
     if (rc == -2) return fail(FTH_EUNSUPPORTED, "no kernel instantiated for ns=%d", c->ns);
     if (rc != 0) return fail(FTH_EDEVICE, "step kernel launch failed (%d): %s", rc, hipGetErrorString(hipGetLastError()));
@@ -401,11 +504,17 @@ size_t fth_footprint_bytes(const fth_matrix* M, int32_t ns, int32_t R, int64_t n
     const size_t rb = precision == FTH_FP64 ? 8 : 4;
     const size_t n = size_t(M->n);
     size_t bytes = 0;
-    if (M->format == FTH_CSR)
+    if (M->format == FTH_CSR) {
         bytes += (n + 1) * 8 + size_t(M->nnz) * (4 + rb);
-    else
-        bytes += n * n * (precision == FTH_FP32_BF16X3 ? 4 : rb);
-    bytes += n * size_t(R) * rb * size_t(3 + std::max(ns, 1));
+        bytes += n * size_t(R) * rb * size_t(3 + ns);
+    } else {
+        const size_t P = (n + 255) / 256 * 256;
+        const size_t ks = P >= 2048 ? 8 : P / 256;
+        bytes += P * P * (precision == FTH_FP32_BF16X3 ? 4 : rb);           // M (hi + lo, or FP64)
+        bytes += 2 * P * size_t(R) * rb + n * size_t(R) * rb * size_t(1 + ns);  // q pair (padded), p and s
+        bytes += ks * P * size_t(R) * rb;                                      // split-K partials
+        if (precision == FTH_FP32_BF16X3) bytes += P * size_t(R) * 4;          // bf16 q split
+    }
     const size_t nout = size_t(npairs) + (acc_diag ? n : 0);
     bytes += nout * 24 + size_t(npairs) * 8;
     bytes += 2 * size_t(ns + 1) * size_t(ns + 1) * rb + 64;
@@ -431,8 +540,10 @@ fth_status fth_create(const fth_matrix* M, const fth_gle* gle, double dt, const 
         if (pairs[k] < 0 || pairs[k] >= M->n) return fail(FTH_EINVAL, "pair index out of range at %lld", (long long)k);
     fth_status st = M->format == FTH_CSR ? check_csr(M) : check_dense(M);
     if (st != FTH_OK) return st;
-    if (M->format == FTH_DENSE) return fail(FTH_EUNSUPPORTED, "dense matrices are not supported by this build yet");
-    if (opt.precision == FTH_FP32_BF16X3) return fail(FTH_EUNSUPPORTED, "split-BF16x3 applies to dense matrices only");
+    if (M->format == FTH_CSR && opt.precision == FTH_FP32_BF16X3)
+        return fail(FTH_EUNSUPPORTED, "split-BF16x3 applies to dense matrices only");
+    if (M->format == FTH_DENSE && opt.precision == FTH_FP32)
+        return fail(FTH_EUNSUPPORTED, "dense matrices use FTH_FP32_BF16X3 or FTH_FP64");
     if (gle && (gle->ns > fth::kNsMax)) return fail(FTH_EUNSUPPORTED, "ns > %d not instantiated", fth::kNsMax);
 
     std::unique_ptr<fth_ctx> c(new fth_ctx());
@@ -455,13 +566,18 @@ fth_status fth_create(const fth_matrix* M, const fth_gle* gle, double dt, const 
     HIP_OK(hipEventCreate(&c->ev1));
 
     // matrix
-    HIP_OK(c->dalloc(reinterpret_cast<void**>(&c->d_row_ptr), sizeof(int64_t) * size_t(M->n + 1)));
-    HIP_OK(hipMemcpy(c->d_row_ptr, M->row_ptr, sizeof(int64_t) * size_t(M->n + 1), hipMemcpyHostToDevice));
-    HIP_OK(c->dalloc(reinterpret_cast<void**>(&c->d_col), sizeof(int32_t) * size_t(M->nnz)));
-    HIP_OK(hipMemcpy(c->d_col, M->col, sizeof(int32_t) * size_t(M->nnz), hipMemcpyHostToDevice));
-    st = c->prec == FTH_FP64 ? upload_converted<double>(c.get(), &c->d_val, M->val, M->nnz, M->value_is_f64)
-                             : upload_converted<float>(c.get(), &c->d_val, M->val, M->nnz, M->value_is_f64);
-    if (st != FTH_OK) return st;
+    if (c->dense()) {
+        st = upload_dense(c.get(), M);
+        if (st != FTH_OK) return st;
+    } else {
+        HIP_OK(c->dalloc(reinterpret_cast<void**>(&c->d_row_ptr), sizeof(int64_t) * size_t(M->n + 1)));
+        HIP_OK(hipMemcpy(c->d_row_ptr, M->row_ptr, sizeof(int64_t) * size_t(M->n + 1), hipMemcpyHostToDevice));
+        HIP_OK(c->dalloc(reinterpret_cast<void**>(&c->d_col), sizeof(int32_t) * size_t(M->nnz)));
+        HIP_OK(hipMemcpy(c->d_col, M->col, sizeof(int32_t) * size_t(M->nnz), hipMemcpyHostToDevice));
+        st = c->prec == FTH_FP64 ? upload_converted<double>(c.get(), &c->d_val, M->val, M->nnz, M->value_is_f64)
+                                 : upload_converted<float>(c.get(), &c->d_val, M->val, M->nnz, M->value_is_f64);
+        if (st != FTH_OK) return st;
+    }
     st = c->prec == FTH_FP64 ? upload_TS<double>(c.get()) : upload_TS<float>(c.get());
     if (st != FTH_OK) return st;
 
@@ -500,6 +616,12 @@ fth_status fth_run(fth_ctx* c, int64_t nsteps, int32_t replicas) {
     }
     const int K = c->opt.steps_per_graph > 0 ? c->opt.steps_per_graph : kDefaultGraphSteps;
     HIP_OK(hipEventRecord(c->ev0, c->stream));
+    if (c->d_qt && c->qt_dirty) {
+        if (fth::launch_qt_from_q(static_cast<const float*>(c->d_q[c->step & 1]), c->d_qt, c->n, c->rows_pad, c->R,
+                                  c->stream) != 0)
+            return fail(FTH_EDEVICE, "q split launch failed");
+        c->qt_dirty = false;
+    }
     int64_t left = nsteps;
     if (left >= K) {
         if (!c->gexec || c->gK != K) {
@@ -615,7 +737,10 @@ fth_status fth_set_state(fth_ctx* c, const double* q, const double* p, const dou
         for (size_t k = 0; k < src.size(); ++k) t[k] = float(src[k]);
         return hipMemcpy(dst, t.data(), sizeof(float) * t.size(), hipMemcpyHostToDevice);
     };
-    if (q) HIP_OK(put(c->d_q[c->step & 1], std::vector<double>(q, q + cnt)));
+    if (q) {
+        HIP_OK(put(c->d_q[c->step & 1], std::vector<double>(q, q + cnt)));
+        c->qt_dirty = true;
+    }
     if (p || s) {
         // read-modify-write of the interleaved (p, s) block
         std::vector<double> psh(cnt * D);
@@ -637,14 +762,85 @@ fth_status fth_set_state(fth_ctx* c, const double* q, const double* p, const dou
     return FTH_OK;
 }
 
+fth_status fth_force(fth_ctx* c, const double* q, double* F) {
+    if (!c || !q || !F) return fail(FTH_EINVAL, "invalid arguments");
+    if (!c->dense()) return fail(FTH_EUNSUPPORTED, "fth_force is provided for dense contexts");
+    if (c->R == 0) return fail(FTH_ESTATE, "replica count not fixed");
+    HIP_OK(hipStreamSynchronize(c->stream));
+    const int64_t P = c->rows_pad, R = c->R, n = c->n;
+    const size_t rb = c->real_bytes();
+    struct Tmp {
+        std::vector<void*> p;
+        ~Tmp() { for (void* x : p) (void)hipFree(x); }
+    } tmp;
+    auto alloc = [&](size_t b) -> void* {
+        void* x = nullptr;
+        if (hipMalloc(&x, b) != hipSuccess) return nullptr;
+        tmp.p.push_back(x);
+        return x;
+    };
+    void* dq = alloc(size_t(P * R) * rb);
+    void* dpart = alloc(size_t(c->ksplit) * size_t(P * R) * rb);
+    int64_t* dstep = static_cast<int64_t*>(alloc(sizeof(int64_t)));
+    uint16_t* dqt = c->prec == FTH_FP32_BF16X3 ? static_cast<uint16_t*>(alloc(size_t(P * R) * 4)) : nullptr;
+    if (!dq || !dpart || !dstep || (c->prec == FTH_FP32_BF16X3 && !dqt)) return fail(FTH_ENOMEM, "scratch allocation failed");
+    HIP_OK(hipMemset(dq, 0, size_t(P * R) * rb));
+    HIP_OK(hipMemset(dstep, 0, sizeof(int64_t)));
+    if (c->prec == FTH_FP64) {
+        HIP_OK(hipMemcpy(dq, q, sizeof(double) * size_t(n * R), hipMemcpyHostToDevice));
+    } else {
+        std::vector<float> t(size_t(n * R));
+        for (size_t k = 0; k < t.size(); ++k) t[k] = float(q[k]);
+        HIP_OK(hipMemcpy(dq, t.data(), sizeof(float) * t.size(), hipMemcpyHostToDevice));
+        HIP_OK(hipMemset(dqt, 0, size_t(P * R) * 4));
+        if (fth::launch_qt_from_q(static_cast<const float*>(dq), dqt, n, P, int32_t(R), c->stream) != 0)
+            return fail(FTH_EDEVICE, "q split launch failed");
+    }
+    fth::DenseGemmArgs g = gemm_args(c, 0);
+    g.qt = dqt;
+    g.q0 = dq;
+    g.q1 = dq;
+    g.step_base = dstep;
+    g.part = dpart;
+    const int rc = c->prec == FTH_FP64 ? fth::launch_gemm_f64(g, c->stream) : fth::launch_gemm_bf16x3(g, c->stream);
+    if (rc != 0) return fail(FTH_EDEVICE, "dense GEMM launch failed (%d)", rc);
+    HIP_OK(hipStreamSynchronize(c->stream));
+    const size_t pc = size_t(c->ksplit) * size_t(P * R);
+    if (c->prec == FTH_FP64) {
+        std::vector<double> part(pc);
+        HIP_OK(hipMemcpy(part.data(), dpart, sizeof(double) * pc, hipMemcpyDeviceToHost));
+        for (int64_t i = 0; i < n; ++i)
+            for (int64_t r = 0; r < R; ++r) {
+                double acc = 0.0;
+                for (int s = 0; s < c->ksplit; ++s) acc = acc + part[(size_t(s) * P + i) * R + r];
+                F[i * R + r] = -acc;
+            }
+    } else {
+        std::vector<float> part(pc);
+        HIP_OK(hipMemcpy(part.data(), dpart, sizeof(float) * pc, hipMemcpyDeviceToHost));
+        for (int64_t i = 0; i < n; ++i)
+            for (int64_t r = 0; r < R; ++r) {
+                float acc = 0.0f;
+                for (int s = 0; s < c->ksplit; ++s) acc = acc + part[(size_t(s) * P + i) * R + r];
+                F[i * R + r] = -double(acc);
+            }
+    }
+    return FTH_OK;
+}
+
 double fth_last_run_ms(const fth_ctx* c) { return c ? c->last_ms : 0.0; }
 
-int32_t fth_launches_per_step(const fth_ctx* c) { return c ? 1 : 0; }
+int32_t fth_launches_per_step(const fth_ctx* c) { return c ? (c->dense() ? 2 : 1) : 0; }
 
 fth_status fth_kernel_name(const fth_ctx* c, char* name, size_t len) {
     if (!c || !name || len == 0) return fail(FTH_EINVAL, "invalid arguments");
-    std::snprintf(name, len, "csr_step_kernel<%s,NS=%d,RPT=%d,NT=%d>", c->prec == FTH_FP64 ? "double" : "float",
-                  c->ns, c->rpt, int(c->nt));
+    if (c->dense())
+        std::snprintf(name, len, "%s<RT=%d,ksplit=%d> + dense_epilogue_kernel<%s,NS=%d,RPT=%d,NT=%d>",
+                      c->prec == FTH_FP64 ? "gemm_f64_kernel" : "gemm_bf16x3_kernel", c->R / 16, c->ksplit,
+                      c->prec == FTH_FP64 ? "double" : "float", c->ns, c->rpt, int(c->nt));
+    else
+        std::snprintf(name, len, "csr_step_kernel<%s,NS=%d,RPT=%d,NT=%d>", c->prec == FTH_FP64 ? "double" : "float",
+                      c->ns, c->rpt, int(c->nt));
     return FTH_OK;
 }
 

@@ -10,14 +10,21 @@ namespace fth {
 // (the paper reports 4 to 10 extra momenta as sufficient, Sec. I).
 constexpr int kNsMax = 10;
 
-// Arguments of one fused sparse step launch (one request).
+// Arguments of one step launch of one request (sparse step or dense
+// epilogue); fields that a kernel does not use are ignored.
 template <typename Real>
-struct CsrStepArgs {
-    // matrix (CSR)
+struct StepArgs {
+    // force source, sparse: CSR rows
     const int64_t* row_ptr;
     const int32_t* col;
     const Real* val;
-    // state: q ping-pong [N][R]; p and s interleaved per row, ps[N][ns+1][R]
+    // force source, dense: split-K partial sums [ksplit][rows_pad][R] of M q_n
+    const Real* part;
+    int32_t ksplit;
+    int64_t rows_pad;
+    // dense split-BF16x3 only: q_{n+1} split into bf16 hi/lo, tiled [rows_pad/8][R][2][8]
+    uint16_t* qt;
+    // state: q ping-pong [rows][R]; p and s interleaved per row, ps[rows][ns+1][R]
     Real* q0;
     Real* q1;
     Real* ps;
@@ -49,8 +56,8 @@ struct CsrStepArgs {
     int64_t row_tiles_padded;  // rounded up to a multiple of 8 (XCD remap)
 };
 
-// Launch shape of the sparse step.
-struct CsrLaunch {
+// Launch shape of a step kernel.
+struct StepLaunch {
     int ns;              // extra GLE momenta (template)
     int rpt;             // replicas per thread (template: 1, 2, 4, 8)
     bool nt;             // streaming (non-temporal) state loads/stores (template)
@@ -58,10 +65,31 @@ struct CsrLaunch {
     int64_t pair_tiles;  // extra workgroups for the selected pairs
 };
 
+// Arguments of the dense split-K force GEMM  part[ks] = M[:, kslice] q_n[kslice, :].
+struct DenseGemmArgs {
+    const void* m_hi;     // bf16 [rows_pad][rows_pad] (split form) or double (FP64 form)
+    const void* m_lo;     // bf16 [rows_pad][rows_pad] (split form only)
+    const uint16_t* qt;   // split form: q_n as bf16 hi/lo, tiled [rows_pad/8][R][2][8]
+    const void* q0;       // FP64 form: q ping-pong buffers [rows_pad][R] (double)
+    const void* q1;
+    const int64_t* step_base;
+    int32_t k;            // in-chunk step offset
+    void* part;           // [ksplit][rows_pad][R] float (split form) or double
+    int64_t rows_pad;
+    int32_t R;
+    int32_t ksplit;
+    int64_t kslice;       // rows_pad / ksplit
+};
+
 // Launch wrappers (defined in the .hip files).
 template <typename Real>
-int launch_csr_step(const CsrStepArgs<Real>& a, const CsrLaunch& L, int k, void* stream);
-
+int launch_csr_step(const StepArgs<Real>& a, const StepLaunch& L, int k, void* stream);
+template <typename Real>
+int launch_dense_epilogue(const StepArgs<Real>& a, const StepLaunch& L, int k, void* stream);
+int launch_gemm_bf16x3(const DenseGemmArgs& g, void* stream);
+int launch_gemm_f64(const DenseGemmArgs& g, void* stream);
+int launch_split_bf16(const float* m, uint16_t* hi, uint16_t* lo, int64_t count, void* stream);
+int launch_qt_from_q(const float* q, uint16_t* qt, int64_t N, int64_t rows_pad, int32_t R, void* stream);
 int launch_advance(int64_t* step_base, int64_t k, void* stream);
 
 // Host FP64 linear algebra (fth_linalg.cpp).

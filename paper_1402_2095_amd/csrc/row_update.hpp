@@ -1,0 +1,203 @@
+// Per-row GLE update shared by the sparse step kernel and the dense
+// epilogue: given acc = (M q_n)_i for the thread's replicas, apply
+//   diagonal accumulator (FP64, block averaged) from q_n,
+//   p += (h/2) F;  (p, s) <- T (p, s) + S xi;  p += (h/2) F;  q' = q + h p
+// with F = -acc, and store p, s and q_{n+1}.
+//
+// Thread mapping: row i is served by TPR = R / RPT consecutive lanes; lane rq
+// owns replicas [rq*RPT, rq*RPT + RPT).  q is [rows][R]; the thermostat part
+// is interleaved per row as ps[rows][ns+1][R] (p first), so one row's
+// momenta are a single contiguous (ns+1)*R block.
+#pragma once
+
+#include <hip/hip_runtime.h>
+
+#include "fth_internal.h"
+#include "noise.hpp"
+
+namespace fth {
+namespace dev {
+
+template <typename Real, int RPT>
+struct alignas(sizeof(Real) * RPT) Vec {
+    Real v[RPT];
+};
+
+template <typename Real, int RPT>
+__device__ __forceinline__ Vec<Real, RPT> load_vec(const Real* p) {
+    return *reinterpret_cast<const Vec<Real, RPT>*>(p);
+}
+
+template <typename Real, int RPT>
+__device__ __forceinline__ void store_vec(Real* p, const Vec<Real, RPT>& v) {
+    *reinterpret_cast<Vec<Real, RPT>*>(p) = v;
+}
+
+// Streaming (non-temporal) forms for state that is touched once per step:
+// when the state does not fit the 256 MB Infinity Cache, keeping it out of
+// L2/MALL leaves those caches to the data that is reused.
+template <typename Real, int RPT, bool NT>
+__device__ __forceinline__ Vec<Real, RPT> load_state(const Real* p) {
+    if constexpr (NT) {
+        Vec<Real, RPT> v;
+#pragma unroll
+        for (int m = 0; m < RPT; ++m) v.v[m] = __builtin_nontemporal_load(p + m);
+        return v;
+    } else {
+        return load_vec<Real, RPT>(p);
+    }
+}
+
+template <typename Real, int RPT, bool NT>
+__device__ __forceinline__ void store_state(Real* p, const Vec<Real, RPT>& v) {
+    if constexpr (NT) {
+#pragma unroll
+        for (int m = 0; m < RPT; ++m) __builtin_nontemporal_store(v.v[m], p + m);
+    } else {
+        store_vec<Real, RPT>(p, v);
+    }
+}
+
+__device__ __forceinline__ float fmaR(float a, float b, float c) { return __builtin_fmaf(a, b, c); }
+__device__ __forceinline__ double fmaR(double a, double b, double c) { return __builtin_fma(a, b, c); }
+
+// Block-averaging accumulator update (one element, one step).
+__device__ __forceinline__ void acc_update(double* blk, double* s1, double* s2, int64_t idx, double x,
+                                           bool close) {
+    const double b = blk[idx] + x;
+    if (close) {
+        s1[idx] = s1[idx] + b;
+        s2[idx] = s2[idx] + b * b;
+        blk[idx] = 0.0;
+    } else {
+        blk[idx] = b;
+    }
+}
+
+__device__ __forceinline__ double group_sum(double x, int tpr) {
+    for (int off = tpr >> 1; off > 0; off >>= 1) x += __shfl_xor(x, off, 64);
+    return x;
+}
+
+// Per-step constants every launch derives from the device step counter.
+struct StepInfo {
+    int64_t n;     // global step index
+    bool acc_on;   // n >= burn_in
+    bool close;    // this step closes a block
+    int rq, r0, slot, tpr;
+};
+
+template <typename Real, int RPT>
+__device__ __forceinline__ StepInfo step_info(const StepArgs<Real>& a, int k) {
+    StepInfo s;
+    s.n = a.step_base[0] + k;
+    s.acc_on = s.n >= a.burn_in;
+    s.close = s.acc_on && ((s.n - a.burn_in + 1) % a.block_len) == 0;
+    s.tpr = 1 << a.lg_tpr;
+    s.rq = threadIdx.x & (s.tpr - 1);
+    s.r0 = s.rq * RPT;
+    s.slot = threadIdx.x >> a.lg_tpr;
+    return s;
+}
+
+// Selected pairs: sum_r q_i^r q_j^r from q_n into the pair accumulators.
+template <typename Real, int RPT>
+__device__ __forceinline__ void pair_update(const StepArgs<Real>& a, const StepInfo& si, const Real* qr, int64_t pk) {
+    using V = Vec<Real, RPT>;
+    const int64_t R = a.R;
+    const int64_t pi = a.pairs[2 * pk], pj = a.pairs[2 * pk + 1];
+    const V qi = load_vec<Real, RPT>(qr + pi * R + si.r0);
+    const V qj = load_vec<Real, RPT>(qr + pj * R + si.r0);
+    double x = 0.0;
+#pragma unroll
+    for (int m = 0; m < RPT; ++m) x += double(qi.v[m]) * double(qj.v[m]);
+    x = group_sum(x, si.tpr);
+    if (si.rq == 0 && si.acc_on) acc_update(a.pblk, a.ps1, a.ps2, pk, x, si.close);
+}
+
+// The thread's slice of one row's state.
+template <typename Real, int NS, int RPT>
+struct RowState {
+    Vec<Real, RPT> q, p;
+    Vec<Real, RPT> s[NS > 0 ? NS : 1];
+};
+
+template <typename Real, int NS, int RPT, bool NT>
+__device__ __forceinline__ RowState<Real, NS, RPT> load_row(const StepArgs<Real>& a, const Real* qr, int64_t i,
+                                                            int r0) {
+    RowState<Real, NS, RPT> st;
+    const int64_t R = a.R;
+    constexpr int D = NS + 1;
+    st.q = load_vec<Real, RPT>(qr + i * R + r0);
+    const Real* psrow = a.ps + i * (D * R) + r0;
+    st.p = load_state<Real, RPT, NT>(psrow);
+#pragma unroll
+    for (int c = 0; c < NS; ++c) st.s[c] = load_state<Real, RPT, NT>(psrow + (c + 1) * R);
+    return st;
+}
+
+template <typename Real, int NS, int RPT>
+__device__ __forceinline__ void row_noise(const StepArgs<Real>& a, const StepInfo& si, int64_t i,
+                                          Real (&xi)[NS + 1][RPT]) {
+#pragma unroll
+    for (int c = 0; c <= NS; ++c)
+        normals<Real, RPT>(a.key0, a.key1, a.stream, uint32_t(i), uint32_t(si.n), uint32_t(c), uint32_t(si.r0),
+                           xi[c]);
+}
+
+// Diagonal accumulation, kicks, exact OU step, drift and stores.  Returns
+// q_{n+1} for the thread's replicas.
+template <typename Real, int NS, int RPT, bool NT>
+__device__ __forceinline__ Vec<Real, RPT> finish_row(const StepArgs<Real>& a, const StepInfo& si, int64_t i,
+                                                     const RowState<Real, NS, RPT>& st, const Real (&acc)[RPT],
+                                                     const Real (&xi)[NS + 1][RPT], Real* qw) {
+    constexpr int D = NS + 1;
+    using V = Vec<Real, RPT>;
+    const int64_t R = a.R;
+    if (a.dblk != nullptr) {
+        double x = 0.0;
+#pragma unroll
+        for (int m = 0; m < RPT; ++m) x += double(st.q.v[m]) * double(st.q.v[m]);
+        x = group_sum(x, si.tpr);
+        if (si.rq == 0 && si.acc_on) acc_update(a.dblk, a.ds1, a.ds2, i, x, si.close);
+    }
+    const Real* T = a.TS;
+    const Real* S = a.TS + D * D;
+    V pn, qn;
+    V sn[NS > 0 ? NS : 1];
+    bool ok = true;
+#pragma unroll
+    for (int m = 0; m < RPT; ++m) {
+        const Real f = -acc[m];
+        Real x[D];
+        x[0] = fmaR(a.hh, f, st.p.v[m]);
+#pragma unroll
+        for (int c = 0; c < NS; ++c) x[c + 1] = st.s[c].v[m];
+        Real y[D];
+#pragma unroll
+        for (int r = 0; r < D; ++r) {
+            Real v = Real(0);
+#pragma unroll
+            for (int c = 0; c < D; ++c) v = fmaR(T[r * D + c], x[c], v);
+#pragma unroll
+            for (int c = 0; c <= r; ++c) v = fmaR(S[r * D + c], xi[c][m], v);
+            y[r] = v;
+        }
+        const Real pnew = fmaR(a.hh, f, y[0]);
+        pn.v[m] = pnew;
+#pragma unroll
+        for (int c = 0; c < NS; ++c) sn[c].v[m] = y[c + 1];
+        qn.v[m] = fmaR(a.h, pnew, st.q.v[m]);
+        ok = ok && __builtin_isfinite(qn.v[m]) && __builtin_isfinite(pnew);
+    }
+    Real* psrow = a.ps + i * (D * R) + si.r0;
+    store_state<Real, RPT, NT>(psrow, pn);
+#pragma unroll
+    for (int c = 0; c < NS; ++c) store_state<Real, RPT, NT>(psrow + (c + 1) * R, sn[c]);
+    store_state<Real, RPT, NT>(qw + i * R + si.r0, qn);
+    if (!ok) atomicOr(a.flag, 1);
+    return qn;
+}
+
+}  // namespace dev
+}  // namespace fth

@@ -26,7 +26,7 @@ EXPORTS = [
     "fth_default_options", "fth_create", "fth_run", "fth_num_outputs", "fth_read",
     "fth_get_accumulators", "fth_get_state", "fth_set_state", "fth_last_run_ms",
     "fth_launches_per_step", "fth_kernel_name", "fth_propagator", "fth_footprint_bytes",
-    "fth_destroy", "fth_last_error", "fth_version", "fth_noise_sample",
+    "fth_destroy", "fth_last_error", "fth_version", "fth_noise_sample", "fth_force",
 ]
 
 
@@ -82,6 +82,7 @@ def lib():
             "fth_last_error": (ctypes.c_char_p, []),
             "fth_version": (ctypes.c_char_p, []),
             "fth_noise_sample": (i32, [u64, ctypes.c_uint32, i64, P, P, P, P, i32, P, P]),
+            "fth_force": (i32, [P, P, P]),
         }
         for name, (res, args) in sig.items():
             f = getattr(L, name)
@@ -210,6 +211,13 @@ def fth_set_state(ctx, q=None, p=None, s=None):
     _check(lib().fth_set_state(ctx, *[_p(a) for a in arrs]))
 
 
+def fth_force(ctx, q):
+    q = np.ascontiguousarray(q, dtype=np.float64)
+    F = np.zeros_like(q)
+    _check(lib().fth_force(ctx, _p(q), _p(F)))
+    return F
+
+
 def fth_last_run_ms(ctx) -> float:
     return float(lib().fth_last_run_ms(ctx))
 
@@ -276,6 +284,9 @@ class Solver:
 
     def set_state(self, q=None, p=None, s=None):
         fth_set_state(self.ctx, q, p, s)
+
+    def force(self, q):
+        return fth_force(self.ctx, q)
 
     @property
     def last_run_ms(self):
