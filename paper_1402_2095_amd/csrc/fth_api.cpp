@@ -74,6 +74,13 @@ struct fth_ctx {
     void* d_part = nullptr;
     uint16_t* d_qt = nullptr;
     bool qt_dirty = true;
+    // small dense systems: persistent single-workgroup kernel, M [n][n] in state precision
+    bool small = false;
+    void* d_msmall = nullptr;
+    size_t small_lds = 0;
+    int small_m_in_lds = 0;
+    std::vector<double> m_host;  // dense M kept until R fixes the path (n <= 4096)
+    bool m_uploaded = false;
     void* d_q[2] = {nullptr, nullptr};
     void* d_ps = nullptr;  // [n][ns+1][R]: p then s_1..s_ns per row
     double* d_acc = nullptr;  // [3][n_out]: blk, s1, s2 (pairs first, then diagonal)
@@ -104,7 +111,8 @@ struct fth_ctx {
 
     size_t real_bytes() const { return prec == FTH_FP64 ? 8 : 4; }
     bool dense() const { return fmt == FTH_DENSE; }
-    int64_t q_rows() const { return dense() ? rows_pad : n; }
+    bool mfma() const { return dense() && !small; }
+    int64_t q_rows() const { return mfma() ? rows_pad : n; }
     int64_t n_out() const { return npairs + (opt.acc_diag ? n : 0); }
 
     hipError_t dalloc(void** p, size_t bytes) {
@@ -268,8 +276,8 @@ fth_status upload_TS(fth_ctx* c) {
 
 // Dense M padded to rows_pad x rows_pad with zeros (rows_pad a multiple of
 // 256): bf16 hi/lo split on the device for the split form, FP64 as is.
-fth_status upload_dense(fth_ctx* c, const fth_matrix* M) {
-    const int64_t n = M->n;
+fth_status upload_dense(fth_ctx* c, const std::vector<double>& M) {
+    const int64_t n = c->n;
     c->rows_pad = (n + 255) / 256 * 256;
     const int64_t P = c->rows_pad;
     c->ksplit = P >= 2048 ? 8 : int(P / 256);
@@ -277,33 +285,20 @@ fth_status upload_dense(fth_ctx* c, const fth_matrix* M) {
     if (c->prec == FTH_FP64) {
         HIP_OK(c->dalloc(&c->d_m_hi, cnt * sizeof(double)));
         HIP_OK(hipMemset(c->d_m_hi, 0, cnt * sizeof(double)));
-        if (M->value_is_f64) {
-            HIP_OK(hipMemcpy2D(c->d_m_hi, size_t(P) * 8, M->dense, size_t(n) * 8, size_t(n) * 8, size_t(n),
-                               hipMemcpyHostToDevice));
-        } else {
-            std::vector<double> row(n);
-            const float* src = static_cast<const float*>(M->dense);
-            for (int64_t i = 0; i < n; ++i) {
-                for (int64_t j = 0; j < n; ++j) row[j] = src[i * n + j];
-                HIP_OK(hipMemcpy(static_cast<double*>(c->d_m_hi) + i * P, row.data(), size_t(n) * 8,
-                                 hipMemcpyHostToDevice));
-            }
-        }
+        HIP_OK(hipMemcpy2D(c->d_m_hi, size_t(P) * 8, M.data(), size_t(n) * 8, size_t(n) * 8, size_t(n),
+                           hipMemcpyHostToDevice));
         return FTH_OK;
     }
+    if (c->prec != FTH_FP32_BF16X3)
+        return fail(FTH_EUNSUPPORTED, "dense systems beyond one workgroup use FTH_FP32_BF16X3 or FTH_FP64");
     float* tmp = nullptr;
     HIP_OK(hipMalloc(&tmp, cnt * sizeof(float)));
     std::unique_ptr<float, hipError_t (*)(void*)> guard(tmp, hipFree);
     HIP_OK(hipMemset(tmp, 0, cnt * sizeof(float)));
-    if (M->value_is_f64) {
-        std::vector<float> row(n);
-        const double* src = static_cast<const double*>(M->dense);
-        for (int64_t i = 0; i < n; ++i) {
-            for (int64_t j = 0; j < n; ++j) row[j] = float(src[i * n + j]);
-            HIP_OK(hipMemcpy(tmp + i * P, row.data(), size_t(n) * 4, hipMemcpyHostToDevice));
-        }
-    } else {
-        HIP_OK(hipMemcpy2D(tmp, size_t(P) * 4, M->dense, size_t(n) * 4, size_t(n) * 4, size_t(n),
+    {
+        std::vector<float> mf(size_t(n) * size_t(n));
+        for (size_t k = 0; k < mf.size(); ++k) mf[k] = float(M[k]);
+        HIP_OK(hipMemcpy2D(tmp, size_t(P) * 4, mf.data(), size_t(n) * 4, size_t(n) * 4, size_t(n),
                            hipMemcpyHostToDevice));
     }
     HIP_OK(c->dalloc(&c->d_m_hi, cnt * sizeof(uint16_t)));
@@ -315,6 +310,34 @@ fth_status upload_dense(fth_ctx* c, const fth_matrix* M) {
     return FTH_OK;
 }
 
+// Small dense systems: M [n][n] in the state precision for the persistent kernel.
+fth_status upload_small(fth_ctx* c, const std::vector<double>& M) {
+    const size_t cnt = M.size();
+    if (c->prec == FTH_FP64) {
+        HIP_OK(c->dalloc(&c->d_msmall, cnt * sizeof(double)));
+        HIP_OK(hipMemcpy(c->d_msmall, M.data(), cnt * sizeof(double), hipMemcpyHostToDevice));
+    } else {
+        std::vector<float> mf(cnt);
+        for (size_t k = 0; k < cnt; ++k) mf[k] = float(M[k]);
+        HIP_OK(c->dalloc(&c->d_msmall, cnt * sizeof(float)));
+        HIP_OK(hipMemcpy(c->d_msmall, mf.data(), cnt * sizeof(float), hipMemcpyHostToDevice));
+    }
+    return FTH_OK;
+}
+
+std::vector<double> dense_to_double(const fth_matrix* M) {
+    const size_t cnt = size_t(M->n) * size_t(M->n);
+    std::vector<double> out(cnt);
+    if (M->value_is_f64)
+        std::memcpy(out.data(), M->dense, cnt * sizeof(double));
+    else
+        for (size_t k = 0; k < cnt; ++k) out[k] = static_cast<const float*>(M->dense)[k];
+    return out;
+}
+
+constexpr int64_t kSmallMaxNR = 4096;       // n * R handled by one workgroup
+constexpr size_t kSmallMaxLds = 64 * 1024;  // LDS budget of the persistent kernel
+
 fth_status ensure_state(fth_ctx* c, int32_t R) {
     if (c->R != 0) {
         if (R != 0 && R != c->R) return fail(FTH_ESTATE, "replica count is fixed at %d", c->R);
@@ -322,14 +345,34 @@ fth_status ensure_state(fth_ctx* c, int32_t R) {
     }
     if (R == 0) R = c->opt.replicas;
     if (R == 0) return fail(FTH_EINVAL, "replica count not given");
-    if (c->dense()) {
-        if (R != 16 && R != 32 && R != 64 && R != 128)
-            return fail(FTH_EUNSUPPORTED, "dense matrices need R in {16, 32, 64, 128} (got %d)", R);
-    } else if (!is_pow2(R) || R > 512) {
-        return fail(FTH_EUNSUPPORTED, "R must be a power of two <= 512 (got %d)", R);
+    if (!is_pow2(R) || R > 512) return fail(FTH_EUNSUPPORTED, "R must be a power of two <= 512 (got %d)", R);
+    int rpt = R >= 4 ? (R > 256 ? 8 : 4) : R;
+    if (c->dense() && !c->m_uploaded) {
+        const int64_t threads = c->n * (R / std::min(R, 4));
+        const size_t rb = c->real_bytes();
+        const size_t lds_base = size_t(c->npairs + (c->opt.acc_diag ? c->n : 0)) * 8 + 2 * size_t(c->n) * R * rb;
+        const bool small = c->n * R <= kSmallMaxNR && R <= 64 && threads <= 1024 && lds_base <= kSmallMaxLds;
+        fth_status st2;
+        if (small) {
+            c->small = true;
+            rpt = std::min(R, 4);
+            c->small_m_in_lds = lds_base + size_t(c->n) * size_t(c->n) * rb <= kSmallMaxLds;
+            c->small_lds = lds_base + (c->small_m_in_lds ? size_t(c->n) * size_t(c->n) * rb : 0);
+            st2 = upload_small(c, c->m_host);
+        } else {
+            if (R != 16 && R != 32 && R != 64 && R != 128)
+                return fail(FTH_EUNSUPPORTED, "dense systems of this size need R in {16, 32, 64, 128} (got %d)", R);
+            st2 = upload_dense(c, c->m_host);
+        }
+        if (st2 != FTH_OK) return st2;
+        c->m_host.clear();
+        c->m_host.shrink_to_fit();
+        c->m_uploaded = true;
+    } else if (c->mfma() && R != 16 && R != 32 && R != 64 && R != 128) {
+        return fail(FTH_EUNSUPPORTED, "dense systems of this size need R in {16, 32, 64, 128} (got %d)", R);
     }
     c->R = R;
-    c->rpt = R >= 4 ? (R > 256 ? 8 : 4) : R;
+    c->rpt = rpt;
     const size_t rb = c->real_bytes();
     const size_t qst = size_t(c->q_rows()) * size_t(R) * rb;
     const size_t st = size_t(c->n) * size_t(R) * rb;
@@ -341,7 +384,7 @@ fth_status ensure_state(fth_ctx* c, int32_t R) {
     HIP_OK(hipMemsetAsync(c->d_q[0], 0, qst, c->stream));
     HIP_OK(hipMemsetAsync(c->d_q[1], 0, qst, c->stream));
     HIP_OK(hipMemsetAsync(c->d_ps, 0, st * size_t(c->ns + 1), c->stream));
-    if (c->dense()) {
+    if (c->mfma()) {
         const size_t pb = size_t(c->ksplit) * size_t(c->rows_pad) * size_t(R) * rb;
         HIP_OK(c->dalloc(&c->d_part, pb));
         HIP_OK(hipMemsetAsync(c->d_part, 0, pb, c->stream));
@@ -366,6 +409,8 @@ fth::StepArgs<Real> step_args(fth_ctx* c) {
     a.ksplit = c->ksplit;
     a.rows_pad = c->rows_pad;
     a.qt = c->d_qt;
+    a.mdense = static_cast<const Real*>(c->d_msmall);
+    a.m_in_lds = c->small_m_in_lds;
     a.q0 = static_cast<Real*>(c->d_q[0]);
     a.q1 = static_cast<Real*>(c->d_q[1]);
     a.ps = static_cast<Real*>(c->d_ps);
@@ -442,6 +487,19 @@ fth_status enqueue_step(fth_ctx* c, int k) {
     }
     if (rc == -2) return fail(FTH_EUNSUPPORTED, "no kernel instantiated for ns=%d", c->ns);
     if (rc != 0) return fail(FTH_EDEVICE, "step kernel launch failed (%d): %s", rc, hipGetErrorString(hipGetLastError()));
+    return FTH_OK;
+}
+
+fth_status enqueue_small(fth_ctx* c, int64_t nsteps) {
+    for (int64_t done = 0; done < nsteps;) {
+        const int K = int(std::min<int64_t>(nsteps - done, 4096));
+        const int rc = c->prec == FTH_FP64
+                           ? fth::launch_small_dense<double>(step_args<double>(c), step_launch(c), K, c->small_lds, c->stream)
+                           : fth::launch_small_dense<float>(step_args<float>(c), step_launch(c), K, c->small_lds, c->stream);
+        if (rc == -2) return fail(FTH_EUNSUPPORTED, "no kernel instantiated for ns=%d", c->ns);
+        if (rc != 0) return fail(FTH_EDEVICE, "small-system kernel launch failed (%d)", rc);
+        done += K;
+    }
     return FTH_OK;
 }
 
@@ -542,8 +600,8 @@ fth_status fth_create(const fth_matrix* M, const fth_gle* gle, double dt, const 
     if (st != FTH_OK) return st;
     if (M->format == FTH_CSR && opt.precision == FTH_FP32_BF16X3)
         return fail(FTH_EUNSUPPORTED, "split-BF16x3 applies to dense matrices only");
-    if (M->format == FTH_DENSE && opt.precision == FTH_FP32)
-        return fail(FTH_EUNSUPPORTED, "dense matrices use FTH_FP32_BF16X3 or FTH_FP64");
+    if (M->format == FTH_DENSE && opt.precision == FTH_FP32 && M->n > kSmallMaxNR)
+        return fail(FTH_EUNSUPPORTED, "dense systems beyond one workgroup use FTH_FP32_BF16X3 or FTH_FP64");
     if (gle && (gle->ns > fth::kNsMax)) return fail(FTH_EUNSUPPORTED, "ns > %d not instantiated", fth::kNsMax);
 
     std::unique_ptr<fth_ctx> c(new fth_ctx());
@@ -567,8 +625,14 @@ fth_status fth_create(const fth_matrix* M, const fth_gle* gle, double dt, const 
 
     // matrix
     if (c->dense()) {
-        st = upload_dense(c.get(), M);
-        if (st != FTH_OK) return st;
+        c->m_host = dense_to_double(M);
+        if (M->n > kSmallMaxNR) {  // cannot take the single-workgroup path for any R
+            st = upload_dense(c.get(), c->m_host);
+            if (st != FTH_OK) return st;
+            c->m_host.clear();
+            c->m_host.shrink_to_fit();
+            c->m_uploaded = true;
+        }
     } else {
         HIP_OK(c->dalloc(reinterpret_cast<void**>(&c->d_row_ptr), sizeof(int64_t) * size_t(M->n + 1)));
         HIP_OK(hipMemcpy(c->d_row_ptr, M->row_ptr, sizeof(int64_t) * size_t(M->n + 1), hipMemcpyHostToDevice));
@@ -623,6 +687,11 @@ fth_status fth_run(fth_ctx* c, int64_t nsteps, int32_t replicas) {
         c->qt_dirty = false;
     }
     int64_t left = nsteps;
+    if (c->small) {
+        st = enqueue_small(c, nsteps);
+        if (st != FTH_OK) return st;
+        left = 0;
+    }
     if (left >= K) {
         if (!c->gexec || c->gK != K) {
             st = build_graph(c, K);
@@ -764,7 +833,7 @@ fth_status fth_set_state(fth_ctx* c, const double* q, const double* p, const dou
 
 fth_status fth_force(fth_ctx* c, const double* q, double* F) {
     if (!c || !q || !F) return fail(FTH_EINVAL, "invalid arguments");
-    if (!c->dense()) return fail(FTH_EUNSUPPORTED, "fth_force is provided for dense contexts");
+    if (!c->mfma()) return fail(FTH_EUNSUPPORTED, "fth_force is provided for dense contexts on the matrix-core path");
     if (c->R == 0) return fail(FTH_ESTATE, "replica count not fixed");
     HIP_OK(hipStreamSynchronize(c->stream));
     const int64_t P = c->rows_pad, R = c->R, n = c->n;
@@ -830,11 +899,14 @@ fth_status fth_force(fth_ctx* c, const double* q, double* F) {
 
 double fth_last_run_ms(const fth_ctx* c) { return c ? c->last_ms : 0.0; }
 
-int32_t fth_launches_per_step(const fth_ctx* c) { return c ? (c->dense() ? 2 : 1) : 0; }
+int32_t fth_launches_per_step(const fth_ctx* c) { return c ? (c->mfma() ? 2 : 1) : 0; }
 
 fth_status fth_kernel_name(const fth_ctx* c, char* name, size_t len) {
     if (!c || !name || len == 0) return fail(FTH_EINVAL, "invalid arguments");
-    if (c->dense())
+    if (c->small)
+        std::snprintf(name, len, "small_dense_kernel<%s,NS=%d,RPT=%d> (persistent, M in %s)",
+                      c->prec == FTH_FP64 ? "double" : "float", c->ns, c->rpt, c->small_m_in_lds ? "LDS" : "global");
+    else if (c->dense())
         std::snprintf(name, len, "%s<RT=%d,ksplit=%d> + dense_epilogue_kernel<%s,NS=%d,RPT=%d,NT=%d>",
                       c->prec == FTH_FP64 ? "gemm_f64_kernel" : "gemm_bf16x3_kernel", c->R / 16, c->ksplit,
                       c->prec == FTH_FP64 ? "double" : "float", c->ns, c->rpt, int(c->nt));

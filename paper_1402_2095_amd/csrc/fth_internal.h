@@ -24,6 +24,9 @@ struct StepArgs {
     int64_t rows_pad;
     // dense split-BF16x3 only: q_{n+1} split into bf16 hi/lo, tiled [rows_pad/8][R][2][8]
     uint16_t* qt;
+    // small dense systems: M [N][N] row-major in state precision; kept in LDS if m_in_lds
+    const Real* mdense;
+    int32_t m_in_lds;
     // state: q ping-pong [rows][R]; p and s interleaved per row, ps[rows][ns+1][R]
     Real* q0;
     Real* q1;
@@ -91,6 +94,9 @@ int launch_gemm_f64(const DenseGemmArgs& g, void* stream);
 int launch_split_bf16(const float* m, uint16_t* hi, uint16_t* lo, int64_t count, void* stream);
 int launch_qt_from_q(const float* q, uint16_t* qt, int64_t N, int64_t rows_pad, int32_t R, void* stream);
 int launch_advance(int64_t* step_base, int64_t k, void* stream);
+// One workgroup advances a small dense system by K steps (and the step counter).
+template <typename Real>
+int launch_small_dense(const StepArgs<Real>& a, const StepLaunch& L, int K, size_t lds_bytes, void* stream);
 
 // Host FP64 linear algebra (fth_linalg.cpp).
 namespace la {

@@ -145,32 +145,19 @@ __device__ __forceinline__ void row_noise(const StepArgs<Real>& a, const StepInf
                            xi[c]);
 }
 
-// Diagonal accumulation, kicks, exact OU step, drift and stores.  Returns
-// q_{n+1} for the thread's replicas.
-template <typename Real, int NS, int RPT, bool NT>
-__device__ __forceinline__ Vec<Real, RPT> finish_row(const StepArgs<Real>& a, const StepInfo& si, int64_t i,
-                                                     const RowState<Real, NS, RPT>& st, const Real (&acc)[RPT],
-                                                     const Real (&xi)[NS + 1][RPT], Real* qw) {
+// Kicks, exact OU step and drift on registers: from (q, p, s) and
+// acc = (M q)_i produce (q', p', s').  Returns false if a value is not finite.
+template <typename Real, int NS, int RPT>
+__device__ __forceinline__ bool ou_update(const Real* T, const Real* S, Real h, Real hh,
+                                          const RowState<Real, NS, RPT>& st, const Real (&acc)[RPT],
+                                          const Real (&xi)[NS + 1][RPT], RowState<Real, NS, RPT>& out) {
     constexpr int D = NS + 1;
-    using V = Vec<Real, RPT>;
-    const int64_t R = a.R;
-    if (a.dblk != nullptr) {
-        double x = 0.0;
-#pragma unroll
-        for (int m = 0; m < RPT; ++m) x += double(st.q.v[m]) * double(st.q.v[m]);
-        x = group_sum(x, si.tpr);
-        if (si.rq == 0 && si.acc_on) acc_update(a.dblk, a.ds1, a.ds2, i, x, si.close);
-    }
-    const Real* T = a.TS;
-    const Real* S = a.TS + D * D;
-    V pn, qn;
-    V sn[NS > 0 ? NS : 1];
     bool ok = true;
 #pragma unroll
     for (int m = 0; m < RPT; ++m) {
         const Real f = -acc[m];
         Real x[D];
-        x[0] = fmaR(a.hh, f, st.p.v[m]);
+        x[0] = fmaR(hh, f, st.p.v[m]);
 #pragma unroll
         for (int c = 0; c < NS; ++c) x[c + 1] = st.s[c].v[m];
         Real y[D];
@@ -183,20 +170,40 @@ __device__ __forceinline__ Vec<Real, RPT> finish_row(const StepArgs<Real>& a, co
             for (int c = 0; c <= r; ++c) v = fmaR(S[r * D + c], xi[c][m], v);
             y[r] = v;
         }
-        const Real pnew = fmaR(a.hh, f, y[0]);
-        pn.v[m] = pnew;
+        const Real pnew = fmaR(hh, f, y[0]);
+        out.p.v[m] = pnew;
 #pragma unroll
-        for (int c = 0; c < NS; ++c) sn[c].v[m] = y[c + 1];
-        qn.v[m] = fmaR(a.h, pnew, st.q.v[m]);
-        ok = ok && __builtin_isfinite(qn.v[m]) && __builtin_isfinite(pnew);
+        for (int c = 0; c < NS; ++c) out.s[c].v[m] = y[c + 1];
+        out.q.v[m] = fmaR(h, pnew, st.q.v[m]);
+        ok = ok && __builtin_isfinite(out.q.v[m]) && __builtin_isfinite(pnew);
     }
-    Real* psrow = a.ps + i * (D * R) + si.r0;
-    store_state<Real, RPT, NT>(psrow, pn);
+    return ok;
+}
+
+// Diagonal accumulation, kicks, exact OU step, drift and stores.  Returns
+// q_{n+1} for the thread's replicas.
+template <typename Real, int NS, int RPT, bool NT>
+__device__ __forceinline__ Vec<Real, RPT> finish_row(const StepArgs<Real>& a, const StepInfo& si, int64_t i,
+                                                     const RowState<Real, NS, RPT>& st, const Real (&acc)[RPT],
+                                                     const Real (&xi)[NS + 1][RPT], Real* qw) {
+    constexpr int D = NS + 1;
+    const int64_t R = a.R;
+    if (a.dblk != nullptr) {
+        double x = 0.0;
 #pragma unroll
-    for (int c = 0; c < NS; ++c) store_state<Real, RPT, NT>(psrow + (c + 1) * R, sn[c]);
-    store_state<Real, RPT, NT>(qw + i * R + si.r0, qn);
+        for (int m = 0; m < RPT; ++m) x += double(st.q.v[m]) * double(st.q.v[m]);
+        x = group_sum(x, si.tpr);
+        if (si.rq == 0 && si.acc_on) acc_update(a.dblk, a.ds1, a.ds2, i, x, si.close);
+    }
+    RowState<Real, NS, RPT> nx;
+    const bool ok = ou_update<Real, NS, RPT>(a.TS, a.TS + D * D, a.h, a.hh, st, acc, xi, nx);
+    Real* psrow = a.ps + i * (D * R) + si.r0;
+    store_state<Real, RPT, NT>(psrow, nx.p);
+#pragma unroll
+    for (int c = 0; c < NS; ++c) store_state<Real, RPT, NT>(psrow + (c + 1) * R, nx.s[c]);
+    store_state<Real, RPT, NT>(qw + i * R + si.r0, nx.q);
     if (!ok) atomicOr(a.flag, 1);
-    return qn;
+    return nx.q;
 }
 
 }  // namespace dev

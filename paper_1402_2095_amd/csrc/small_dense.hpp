@@ -1,0 +1,182 @@
+// Persistent single-workgroup step loop for small dense systems (N * R up
+// to a few thousand), where one launch per step would be launch-bound.
+//
+// One workgroup of N * TPR threads (TPR = R / RPT) runs K steps per launch:
+//   - M (if it fits) and both q buffers live in LDS; each thread keeps its
+//     row slice of p and s in registers for the whole launch;
+//   - the block sums of the accumulators live in LDS; s1 / s2 in global
+//     memory are touched only when a block closes;
+//   - one workgroup barrier per step separates reading q_n from writing
+//     q_{n+1}, which go to alternating LDS buffers.
+// The arithmetic of a step is the same as in the sparse and dense kernels
+// (row_update.hpp), so the trajectory matches them up to the order of the
+// force sum.
+#pragma once
+
+#include <hip/hip_runtime.h>
+
+#include "csr_step.hpp"
+
+namespace fth {
+namespace dev {
+
+template <typename Real, int NS, int RPT>
+__global__ __launch_bounds__(1024) void small_dense_kernel(const StepArgs<Real> a, const int K) {
+    extern __shared__ double smem_d[];
+    constexpr int D = NS + 1;
+    using V = Vec<Real, RPT>;
+    const int64_t N = a.N, R = a.R;
+    const int tid = threadIdx.x, nthr = blockDim.x;
+    const int tpr = 1 << a.lg_tpr;
+    const int rq = tid & (tpr - 1), r0 = rq * RPT;
+    const int64_t i = tid >> a.lg_tpr;
+    const bool active = i < N;
+    const int64_t nd = a.dblk != nullptr ? N : 0;
+    // LDS layout: block sums (FP64) | q[2][N][R] | M[N][N] (if in LDS)
+    double* bl = smem_d;
+    Real* qb = reinterpret_cast<Real*>(bl + a.npairs + nd);
+    const Real* Mx = a.mdense;
+    if (a.m_in_lds) {
+        Real* Ml = qb + 2 * N * R;
+        for (int64_t x = tid; x < N * N; x += nthr) Ml[x] = a.mdense[x];
+        Mx = Ml;
+    }
+    const int64_t n0 = a.step_base[0];
+    const Real* qg = (n0 & 1) ? a.q1 : a.q0;
+    for (int64_t x = tid; x < N * R; x += nthr) qb[(n0 & 1) * N * R + x] = qg[x];
+    for (int64_t x = tid; x < a.npairs; x += nthr) bl[x] = a.pblk[x];
+    for (int64_t x = tid; x < nd; x += nthr) bl[a.npairs + x] = a.dblk[x];
+
+    RowState<Real, NS, RPT> st;
+    if (active) {
+        st.q = load_vec<Real, RPT>(qg + i * R + r0);
+        const Real* psrow = a.ps + i * (D * R) + r0;
+        st.p = load_vec<Real, RPT>(psrow);
+#pragma unroll
+        for (int c = 0; c < NS; ++c) st.s[c] = load_vec<Real, RPT>(psrow + (c + 1) * R);
+    }
+    const Real* T = a.TS;
+    const Real* S = a.TS + D * D;
+    bool ok = true;
+    __syncthreads();
+
+    for (int k = 0; k < K; ++k) {
+        const int64_t n = n0 + k;
+        const bool acc_on = n >= a.burn_in;
+        const bool close = acc_on && ((n - a.burn_in + 1) % a.block_len) == 0;
+        const Real* qr = qb + (n & 1) * N * R;
+        Real* qw = qb + ((n + 1) & 1) * N * R;
+        if (acc_on) {
+            for (int64_t pk = tid; pk < a.npairs; pk += nthr) {
+                const int64_t pa = a.pairs[2 * pk], pb = a.pairs[2 * pk + 1];
+                double x = 0.0;
+                for (int64_t r = 0; r < R; ++r) x += double(qr[pa * R + r]) * double(qr[pb * R + r]);
+                const double b = bl[pk] + x;
+                if (close) {
+                    a.ps1[pk] = a.ps1[pk] + b;
+                    a.ps2[pk] = a.ps2[pk] + b * b;
+                    bl[pk] = 0.0;
+                } else {
+                    bl[pk] = b;
+                }
+            }
+        }
+        if (active) {
+            Real acc[RPT];
+#pragma unroll
+            for (int m = 0; m < RPT; ++m) acc[m] = Real(0);
+            for (int64_t j = 0; j < N; ++j) {
+                const Real mij = Mx[i * N + j];
+                const V qj = load_vec<Real, RPT>(qr + j * R + r0);
+#pragma unroll
+                for (int m = 0; m < RPT; ++m) acc[m] = fmaR(mij, qj.v[m], acc[m]);
+            }
+            if (nd) {
+                double x = 0.0;
+#pragma unroll
+                for (int m = 0; m < RPT; ++m) x += double(st.q.v[m]) * double(st.q.v[m]);
+                x = group_sum(x, tpr);
+                if (rq == 0 && acc_on) {
+                    const double b = bl[a.npairs + i] + x;
+                    if (close) {
+                        a.ds1[i] = a.ds1[i] + b;
+                        a.ds2[i] = a.ds2[i] + b * b;
+                        bl[a.npairs + i] = 0.0;
+                    } else {
+                        bl[a.npairs + i] = b;
+                    }
+                }
+            }
+            Real xi[NS + 1][RPT];
+#pragma unroll
+            for (int c = 0; c <= NS; ++c)
+                normals<Real, RPT>(a.key0, a.key1, a.stream, uint32_t(i), uint32_t(n), uint32_t(c), uint32_t(r0),
+                                   xi[c]);
+            RowState<Real, NS, RPT> nx;
+            ok = ou_update<Real, NS, RPT>(T, S, a.h, a.hh, st, acc, xi, nx) && ok;
+            store_vec<Real, RPT>(qw + i * R + r0, nx.q);
+            st = nx;
+        }
+        __syncthreads();
+    }
+    const int64_t nend = n0 + K;
+    Real* qgo = (nend & 1) ? a.q1 : a.q0;
+    if (active) {
+        store_vec<Real, RPT>(qgo + i * R + r0, st.q);
+        Real* psrow = a.ps + i * (D * R) + r0;
+        store_vec<Real, RPT>(psrow, st.p);
+#pragma unroll
+        for (int c = 0; c < NS; ++c) store_vec<Real, RPT>(psrow + (c + 1) * R, st.s[c]);
+    }
+    for (int64_t x = tid; x < a.npairs; x += nthr) a.pblk[x] = bl[x];
+    for (int64_t x = tid; x < nd; x += nthr) a.dblk[x] = bl[a.npairs + x];
+    if (!ok) atomicOr(a.flag, 1);
+    __syncthreads();
+    if (tid == 0) const_cast<int64_t*>(a.step_base)[0] = nend;
+}
+
+template <typename Real, int NS>
+const void* pick_small_rpt(int rpt) {
+    switch (rpt) {
+        case 1: return reinterpret_cast<const void*>(&small_dense_kernel<Real, NS, 1>);
+        case 2: return reinterpret_cast<const void*>(&small_dense_kernel<Real, NS, 2>);
+        case 4: return reinterpret_cast<const void*>(&small_dense_kernel<Real, NS, 4>);
+        default: return nullptr;
+    }
+}
+
+template <typename Real>
+const void* pick_small(int ns, int rpt) {
+    switch (ns) {
+        case 0: return pick_small_rpt<Real, 0>(rpt);
+        case 1: return pick_small_rpt<Real, 1>(rpt);
+        case 2: return pick_small_rpt<Real, 2>(rpt);
+        case 3: return pick_small_rpt<Real, 3>(rpt);
+        case 4: return pick_small_rpt<Real, 4>(rpt);
+        case 5: return pick_small_rpt<Real, 5>(rpt);
+        case 6: return pick_small_rpt<Real, 6>(rpt);
+        case 7: return pick_small_rpt<Real, 7>(rpt);
+        case 8: return pick_small_rpt<Real, 8>(rpt);
+        case 9: return pick_small_rpt<Real, 9>(rpt);
+        case 10: return pick_small_rpt<Real, 10>(rpt);
+        default: return nullptr;
+    }
+}
+
+}  // namespace dev
+
+template <typename Real>
+int launch_small_dense_impl(const StepArgs<Real>& a, const StepLaunch& L, int K, size_t lds_bytes, void* stream) {
+    const void* fn = dev::pick_small<Real>(L.ns, L.rpt);
+    if (fn == nullptr) return -2;
+    const int64_t threads = a.N << a.lg_tpr;
+    const int block = int((threads + 63) / 64 * 64);
+    if (block > 1024) return -3;
+    StepArgs<Real> copy = a;
+    int k = K;
+    void* args[] = {&copy, &k};
+    hipError_t e = hipLaunchKernel(fn, dim3(1), dim3(unsigned(block)), args, lds_bytes, static_cast<hipStream_t>(stream));
+    return e == hipSuccess ? 0 : -1;
+}
+
+}  // namespace fth

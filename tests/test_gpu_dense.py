@@ -134,12 +134,15 @@ def test_dense_repeatable_and_resume():
         assert np.array_equal(x, y)
 
 
-def test_dense_rejects_unsupported_shapes():
-    M, h = dense_case(64, 1)
+def test_dense_path_selection_and_unsupported_shapes():
     g = fi.load_gle("invsqrt_ns4")
+    M, h = dense_case(64, 1)
+    small = fth.Solver(M, g.A_p, g.C_p, h, replicas=8, precision=fth.FTH_FP32_BF16X3).run(1)
+    assert "small_dense_kernel" in small.kernel_name     # N R <= 4096: one persistent workgroup
+    M, h = dense_case(4200, 1)
     with pytest.raises(fth.FthError) as e:
         fth.Solver(M, g.A_p, g.C_p, h, replicas=8, precision=fth.FTH_FP32_BF16X3).run(1)
-    assert e.value.status == fth.FTH_EUNSUPPORTED
+    assert e.value.status == fth.FTH_EUNSUPPORTED         # matrix-core path needs R in {16..128}
     with pytest.raises(fth.FthError) as e:
         fth.Solver(M, g.A_p, g.C_p, h, replicas=16, precision=fth.FTH_FP32)
     assert e.value.status == fth.FTH_EUNSUPPORTED
