@@ -25,7 +25,7 @@
 // M is row-major, so an A fragment is 16 contiguous bytes (bf16) of one
 // row.  The bf16 B fragment needs 8 consecutive k of one column, so q_n is
 // kept as qt[k/8][col][hi|lo][k%8] (written by the epilogue): a k-step of
-// 32 is one contiguous 128*R-byte chunk, staged through LDS and shared by
+// 64 is one contiguous 256*R-byte chunk, staged through LDS and shared by
 // the four waves.  The f64 B fragment is one element, so q_n [k][col] is
 // staged as is; within a k-step of 16, lane group g handles k = 4g + t at
 // substep t, which makes each lane's A data 4 contiguous doubles.
@@ -82,12 +82,18 @@ __device__ __forceinline__ void scatter_chunk(T* __restrict__ dst, const T (&src
 }
 
 // ------------------------------------------------------ split-BF16x3 GEMM
+// A k-step covers 64 consecutive k, so the four lane groups of a row read its
+// whole 128-byte line of M_hi (and of M_lo) at once: a line is never half
+// used and evicted before its second half is read.  Inside a k-step the k
+// order is permuted (a sum may be taken in any order): lane group g owns
+// k = 16 g + 8 t + (0..7) in substep t = 0, 1, so its A data are 32
+// contiguous bytes per row, and its B fragment is q-chunk block 2 g + t.
 template <int RT>
 __global__ __launch_bounds__(256, 2) void gemm_bf16x3_kernel(const DenseGemmArgs g) {
     constexpr int R = 16 * RT;
     constexpr int BM = 128;  // rows per workgroup: 4 waves x 32
-    constexpr int KS = 32;   // k per step
-    constexpr int CHUNK = (KS / 8) * R * 2;  // u32x4 (16 B) per staged k-step: [4][R][hi|lo]
+    constexpr int KS = 64;   // k per step
+    constexpr int CHUNK = (KS / 8) * R * 2;  // 16-byte units per staged k-step: [8][R][hi|lo]
     __shared__ u32x4 qs[2][CHUNK];
 
     const int ks = blockIdx.x % g.ksplit;
@@ -103,9 +109,9 @@ __global__ __launch_bounds__(256, 2) void gemm_bf16x3_kernel(const DenseGemmArgs
     const u32x4* qsrc = reinterpret_cast<const u32x4*>(g.qt);
 
     const int64_t row0 = m0 + 32 * w + lr;  // rows row0 and row0 + 16
-    const uint16_t* a_hi0 = mh + row0 * P + 8 * lg;
+    const uint16_t* a_hi0 = mh + row0 * P + 16 * lg;
     const uint16_t* a_hi1 = a_hi0 + 16 * P;
-    const uint16_t* a_lo0 = ml + row0 * P + 8 * lg;
+    const uint16_t* a_lo0 = ml + row0 * P + 16 * lg;
     const uint16_t* a_lo1 = a_lo0 + 16 * P;
 
     f32x4 acc[2][RT];
@@ -116,38 +122,44 @@ __global__ __launch_bounds__(256, 2) void gemm_bf16x3_kernel(const DenseGemmArgs
 
     constexpr int PER_THREAD = (CHUNK + 255) / 256;
     u32x4 rq[PER_THREAD];
-    u32x4 ra0, ra1, ra2, ra3;
+    u32x4 ra[8];  // [row 0/1][hi/lo][substep 0/1]
 #define FTH_BF16_FETCH(J)                                                          \
     {                                                                              \
         const int64_t kf = kbeg + int64_t(J) * KS;                                 \
         gather_chunk<u32x4, CHUNK, PER_THREAD>(rq, qsrc + (kf / 8) * R * 2);       \
-        ra0 = *reinterpret_cast<const u32x4*>(a_hi0 + kf);                         \
-        ra1 = *reinterpret_cast<const u32x4*>(a_hi1 + kf);                         \
-        ra2 = *reinterpret_cast<const u32x4*>(a_lo0 + kf);                         \
-        ra3 = *reinterpret_cast<const u32x4*>(a_lo1 + kf);                         \
+        ra[0] = *reinterpret_cast<const u32x4*>(a_hi0 + kf);                       \
+        ra[1] = *reinterpret_cast<const u32x4*>(a_hi0 + kf + 8);                   \
+        ra[2] = *reinterpret_cast<const u32x4*>(a_lo0 + kf);                       \
+        ra[3] = *reinterpret_cast<const u32x4*>(a_lo0 + kf + 8);                   \
+        ra[4] = *reinterpret_cast<const u32x4*>(a_hi1 + kf);                       \
+        ra[5] = *reinterpret_cast<const u32x4*>(a_hi1 + kf + 8);                   \
+        ra[6] = *reinterpret_cast<const u32x4*>(a_lo1 + kf);                       \
+        ra[7] = *reinterpret_cast<const u32x4*>(a_lo1 + kf + 8);                   \
     }
     FTH_BF16_FETCH(0)
     for (int j = 0; j < nsteps; ++j) {
         u32x4* buf = qs[j & 1];
         scatter_chunk<u32x4, CHUNK, PER_THREAD>(buf, rq);
-        const bf16x8 ahi0 = __builtin_bit_cast(bf16x8, ra0);
-        const bf16x8 ahi1 = __builtin_bit_cast(bf16x8, ra1);
-        const bf16x8 alo0 = __builtin_bit_cast(bf16x8, ra2);
-        const bf16x8 alo1 = __builtin_bit_cast(bf16x8, ra3);
+        bf16x8 a[8];
+#pragma unroll
+        for (int u = 0; u < 8; ++u) a[u] = __builtin_bit_cast(bf16x8, ra[u]);
         if (j + 1 < nsteps) FTH_BF16_FETCH(j + 1)
         __syncthreads();
 #pragma unroll
-        for (int c = 0; c < RT; ++c) {
-            const u32x4* bsrc = buf + (lg * R + 16 * c + lr) * 2;
-            const bf16x8 bhi = __builtin_bit_cast(bf16x8, bsrc[0]);
-            const bf16x8 blo = __builtin_bit_cast(bf16x8, bsrc[1]);
-            acc[0][c] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(ahi0, bhi, acc[0][c], 0, 0, 0);
-            acc[1][c] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(ahi1, bhi, acc[1][c], 0, 0, 0);
-            acc[0][c] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(ahi0, blo, acc[0][c], 0, 0, 0);
-            acc[1][c] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(ahi1, blo, acc[1][c], 0, 0, 0);
-            acc[0][c] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(alo0, bhi, acc[0][c], 0, 0, 0);
-            acc[1][c] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(alo1, bhi, acc[1][c], 0, 0, 0);
-        }
+        for (int t = 0; t < 2; ++t)
+#pragma unroll
+            for (int c = 0; c < RT; ++c) {
+                const u32x4* bsrc = buf + ((2 * lg + t) * R + 16 * c + lr) * 2;
+                const bf16x8 bhi = __builtin_bit_cast(bf16x8, bsrc[0]);
+                const bf16x8 blo = __builtin_bit_cast(bf16x8, bsrc[1]);
+                // row tile 0: a[0 + t] (hi), a[2 + t] (lo); row tile 1: a[4 + t], a[6 + t]
+                acc[0][c] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(a[0 + t], bhi, acc[0][c], 0, 0, 0);
+                acc[1][c] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(a[4 + t], bhi, acc[1][c], 0, 0, 0);
+                acc[0][c] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(a[0 + t], blo, acc[0][c], 0, 0, 0);
+                acc[1][c] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(a[4 + t], blo, acc[1][c], 0, 0, 0);
+                acc[0][c] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(a[2 + t], bhi, acc[0][c], 0, 0, 0);
+                acc[1][c] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(a[6 + t], bhi, acc[1][c], 0, 0, 0);
+            }
     }
 #undef FTH_BF16_FETCH
     float* part = static_cast<float*>(g.part) + int64_t(ks) * P * R;

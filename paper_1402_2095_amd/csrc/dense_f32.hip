@@ -24,7 +24,7 @@ __global__ void qt_from_q_kernel(const float* __restrict__ q, uint16_t* __restri
 }  // namespace dev
 
 int launch_gemm_bf16x3(const DenseGemmArgs& g, void* stream) {
-    if (g.rows_pad % 128 != 0 || g.kslice % 32 != 0 || g.kslice * g.ksplit != g.rows_pad) return -3;
+    if (g.rows_pad % 128 != 0 || g.kslice % 64 != 0 || g.kslice * g.ksplit != g.rows_pad) return -3;
     const int64_t grid = (g.rows_pad / 128) * g.ksplit;
     const hipStream_t s = static_cast<hipStream_t>(stream);
     switch (g.R) {
