@@ -207,6 +207,87 @@ fth_status fth_noise_sample(uint64_t seed, uint32_t stream, int64_t count, const
 size_t fth_footprint_bytes(const fth_matrix* M, int32_t ns, int32_t replicas,
                            int64_t npairs, int32_t acc_diag, int32_t precision);
 
+/* ------------------------------------------------------------------ */
+/* Serving layer: a request loop over many solves that share one GPU.   */
+/* ------------------------------------------------------------------ */
+/* Requests arrive at any time (fth_server_submit).  Each fth_server_tick
+ * admits queued requests in arrival order while their device footprint
+ * (fth_footprint_bytes) fits the remaining HBM budget, advances every
+ * running request by steps_per_tick steps, reads their stderr summaries and
+ * retires the ones that reached their target (or max_steps), freeing their
+ * memory for the queue.  Sparse FP32 requests with the same ns are packed
+ * into one persistent kernel per step (a device work list of row and pair
+ * tiles, captured as one hipGraph per tick), so work of concurrent requests
+ * of uneven size overlaps on the device; dense and FP64 requests run their
+ * own kernels in the same tick.  A request's trajectory depends only on its
+ * own inputs (matrix, GLE, dt, seed, stream_id), not on what runs beside it.
+ * A server is not thread-safe. */
+typedef struct fth_server fth_server;
+
+typedef struct {
+    size_t hbm_budget;       /* bytes of device memory for requests; 0: 80% of free */
+    int32_t steps_per_tick;  /* steps per tick (and between stderr checks); 0: 200 */
+    int32_t max_active;      /* running requests at most; 0: 64 */
+    int32_t min_blocks;      /* complete blocks needed before a stderr counts; 0: 8 */
+} fth_server_options;
+
+typedef struct {
+    fth_matrix M;            /* deep-copied at submit */
+    fth_gle gle;             /* deep-copied at submit */
+    double dt;
+    const int32_t* pairs;    /* [npairs][2], deep-copied at submit */
+    int64_t npairs;
+    int32_t replicas;        /* 0: 32 for CSR, 64 for dense */
+    int32_t precision;       /* FTH_FP32 (CSR, packed), FTH_FP64, FTH_FP32_BF16X3 (dense) */
+    uint64_t seed;
+    uint32_t stream_id;      /* noise stream; 0: the request id */
+    int64_t burn_in;
+    int64_t block_len;       /* 0: 100 */
+    double target_rel_stderr;/* stop when every estimate's stderr / scale <= target;
+                                scale = sqrt(est_ii est_jj) when both diagonals are
+                                among the request's pairs, else |est| */
+    int64_t max_steps;       /* stop at the first tick boundary at or after this many
+                                steps (0: no limit); requests advance in whole ticks */
+} fth_request;
+
+typedef enum {
+    FTH_REQ_QUEUED = 0, FTH_REQ_RUNNING = 1, FTH_REQ_DONE = 2, FTH_REQ_FAILED = 3, FTH_REQ_CANCELLED = 4
+} fth_request_state;
+
+typedef struct {
+    int32_t state;           /* fth_request_state */
+    int32_t status;          /* fth_status of a failure, else FTH_OK */
+    int64_t steps;           /* steps taken */
+    int64_t nblocks;         /* complete blocks */
+    double max_rel_stderr;   /* at the last check (+inf before min_blocks) */
+    double t_submit, t_start, t_finish;  /* seconds on the server's clock (-1: not yet) */
+    int64_t n_out;           /* number of estimates (= npairs) */
+    int32_t replicas;
+    int32_t packed;          /* 1 if run by the packed multi-request kernel */
+    size_t footprint;        /* device bytes reserved while running */
+} fth_request_info;
+
+/* Create a server on the current device.  opt may be NULL (defaults). */
+fth_status fth_server_create(const fth_server_options* opt, fth_server** out);
+/* Queue a request; *id receives its id (>= 1).  FTH_EINVAL on invalid input,
+ * FTH_ENOMEM if its footprint exceeds the whole budget. */
+fth_status fth_server_submit(fth_server* srv, const fth_request* req, uint64_t* id);
+/* Admit, run one tick of steps for every running request, check, retire. */
+fth_status fth_server_tick(fth_server* srv);
+/* State of a request (any state). */
+fth_status fth_server_poll(fth_server* srv, uint64_t id, fth_request_info* info);
+/* Estimates and standard errors of a finished (or running) request
+ * (len >= n_out, either pointer may be NULL). */
+fth_status fth_server_result(fth_server* srv, uint64_t id, double* est, double* se, int64_t len);
+/* Cancel a queued or running request (its memory is released). */
+fth_status fth_server_cancel(fth_server* srv, uint64_t id);
+/* Seconds since the server was created (its clock). */
+double fth_server_clock(const fth_server* srv);
+/* Counts of queued and running requests, and bytes reserved. */
+fth_status fth_server_stats(const fth_server* srv, int64_t* queued, int64_t* running, size_t* reserved);
+/* Release the server and every request in it.  NULL is accepted. */
+fth_status fth_server_destroy(fth_server* srv);
+
 /* Release the context and its device memory.  NULL is accepted. */
 fth_status fth_destroy(fth_ctx* ctx);
 

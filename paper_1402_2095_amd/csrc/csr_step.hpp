@@ -28,27 +28,12 @@
 namespace fth {
 namespace dev {
 
+// One row of one request: gather, noise, force, shared row update.
 template <typename Real, int NS, int RPT, bool NT>
-__global__ __launch_bounds__(256) void csr_step_kernel(const StepArgs<Real> a, const int k) {
+__device__ __forceinline__ void csr_row(const StepArgs<Real>& a, const StepInfo& si, int64_t i, const Real* qr,
+                                        Real* qw) {
     using V = Vec<Real, RPT>;
-    const StepInfo si = step_info<Real, RPT>(a, k);
-    const Real* __restrict__ qr = (si.n & 1) ? a.q1 : a.q0;
-    Real* __restrict__ qw = (si.n & 1) ? a.q0 : a.q1;
-    const int per_block = blockDim.x >> a.lg_tpr;
-    const int64_t b = blockIdx.x;
     const int64_t R = a.R;
-
-    if (b >= a.row_tiles_padded) {
-        const int64_t pk = (b - a.row_tiles_padded) * per_block + si.slot;
-        if (pk < a.npairs) pair_update<Real, RPT>(a, si, qr, pk);
-        return;
-    }
-    const int64_t per = a.row_tiles_padded >> 3;
-    const int64_t t = (b & 7) * per + (b >> 3);
-    if (t >= a.row_tiles) return;
-    const int64_t i = t * per_block + si.slot;
-    if (i >= a.N) return;
-
     constexpr int G = 8;  // CSR entries gathered per batch
     const int64_t kb = a.row_ptr[i], ke = a.row_ptr[i + 1];
     const RowState<Real, NS, RPT> st = load_row<Real, NS, RPT, NT>(a, qr, i, si.r0);
@@ -84,6 +69,27 @@ __global__ __launch_bounds__(256) void csr_step_kernel(const StepArgs<Real> a, c
         for (int m = 0; m < RPT; ++m) acc[m] = fmaR(v, q.v[m], acc[m]);
     }
     (void)finish_row<Real, NS, RPT, NT>(a, si, i, st, acc, xi, qw);
+}
+
+template <typename Real, int NS, int RPT, bool NT>
+__global__ __launch_bounds__(256) void csr_step_kernel(const StepArgs<Real> a, const int k) {
+    const StepInfo si = step_info<Real, RPT>(a, k);
+    const Real* __restrict__ qr = (si.n & 1) ? a.q1 : a.q0;
+    Real* __restrict__ qw = (si.n & 1) ? a.q0 : a.q1;
+    const int per_block = blockDim.x >> a.lg_tpr;
+    const int64_t b = blockIdx.x;
+
+    if (b >= a.row_tiles_padded) {
+        const int64_t pk = (b - a.row_tiles_padded) * per_block + si.slot;
+        if (pk < a.npairs) pair_update<Real, RPT>(a, si, qr, pk);
+        return;
+    }
+    const int64_t per = a.row_tiles_padded >> 3;
+    const int64_t t = (b & 7) * per + (b >> 3);
+    if (t >= a.row_tiles) return;
+    const int64_t i = t * per_block + si.slot;
+    if (i >= a.N) return;
+    csr_row<Real, NS, RPT, NT>(a, si, i, qr, qw);
 }
 
 // ---------------------------------------------------------------- dispatch

@@ -12,10 +12,10 @@
 #include <string>
 #include <vector>
 
-#include "../../include/fth.h"
-#include "fth_internal.h"
+#include "fth_ctx.hpp"
 
-namespace {
+namespace fth {
+namespace host {
 
 thread_local std::string g_last_error;
 
@@ -29,13 +29,6 @@ fth_status fail(fth_status st, const char* fmt, ...) {
     return st;
 }
 
-#define HIP_OK(expr)                                                                          \
-    do {                                                                                      \
-        hipError_t e_ = (expr);                                                               \
-        if (e_ != hipSuccess)                                                                 \
-            return fail(e_ == hipErrorOutOfMemory ? FTH_ENOMEM : FTH_EDEVICE, "%s: %s", #expr, \
-                        hipGetErrorString(e_));                                               \
-    } while (0)
 
 constexpr int kDefaultGraphSteps = 64;
 
@@ -46,85 +39,6 @@ int ilog2(int64_t x) {
     return r;
 }
 
-}  // namespace
-
-struct fth_ctx {
-    // problem
-    int64_t n = 0;
-    int fmt = FTH_CSR;
-    int prec = FTH_FP32;
-    int ns = 0;
-    double h = 0.0;
-    fth_options opt{};
-    int64_t npairs = 0;
-    int64_t nnz = 0;
-    std::vector<double> T, S;
-    // device buffers
-    std::vector<void*> allocs;
-    int64_t* d_row_ptr = nullptr;
-    int32_t* d_col = nullptr;
-    void* d_val = nullptr;
-    void* d_TS = nullptr;
-    int32_t* d_pairs = nullptr;
-    // dense: M padded to rows_pad x rows_pad (bf16 hi/lo, or double), split-K partials, bf16 q split
-    int64_t rows_pad = 0;
-    int ksplit = 1;
-    void* d_m_hi = nullptr;
-    void* d_m_lo = nullptr;
-    void* d_part = nullptr;
-    uint16_t* d_qt = nullptr;
-    bool qt_dirty = true;
-    // small dense systems: persistent single-workgroup kernel, M [n][n] in state precision
-    bool small = false;
-    void* d_msmall = nullptr;
-    size_t small_lds = 0;
-    int small_m_in_lds = 0;
-    std::vector<double> m_host;  // dense M kept until R fixes the path (n <= 4096)
-    bool m_uploaded = false;
-    void* d_q[2] = {nullptr, nullptr};
-    void* d_ps = nullptr;  // [n][ns+1][R]: p then s_1..s_ns per row
-    double* d_acc = nullptr;  // [3][n_out]: blk, s1, s2 (pairs first, then diagonal)
-    int64_t* d_step = nullptr;
-    int32_t* d_flag = nullptr;
-    // schedule
-    int R = 0;
-    int rpt = 0;
-    bool nt = false;  // streaming state access (state larger than the Infinity Cache)
-    int block = 256;
-    hipStream_t stream = nullptr;
-    hipEvent_t ev0 = nullptr, ev1 = nullptr;
-    hipGraphExec_t gexec = nullptr;
-    int gK = 0;
-    int64_t step = 0;
-    bool poisoned = false;
-    double last_ms = 0.0;
-    int device = 0;
-
-    ~fth_ctx() {
-        if (gexec) (void)hipGraphExecDestroy(gexec);
-        if (ev0) (void)hipEventDestroy(ev0);
-        if (ev1) (void)hipEventDestroy(ev1);
-        if (stream) (void)hipStreamSynchronize(stream);
-        for (void* p : allocs) (void)hipFree(p);
-        if (stream) (void)hipStreamDestroy(stream);
-    }
-
-    size_t real_bytes() const { return prec == FTH_FP64 ? 8 : 4; }
-    bool dense() const { return fmt == FTH_DENSE; }
-    bool mfma() const { return dense() && !small; }
-    int64_t q_rows() const { return mfma() ? rows_pad : n; }
-    int64_t n_out() const { return npairs + (opt.acc_diag ? n : 0); }
-
-    hipError_t dalloc(void** p, size_t bytes) {
-        *p = nullptr;
-        if (bytes == 0) bytes = 256;
-        hipError_t e = hipMalloc(p, bytes);
-        if (e == hipSuccess) allocs.push_back(*p);
-        return e;
-    }
-};
-
-namespace {
 
 // ------------------------------------------------------------------ checks
 fth_status check_csr(const fth_matrix* M) {
@@ -533,7 +447,53 @@ fth_status build_graph(fth_ctx* c, int K) {
     return FTH_OK;
 }
 
-}  // namespace
+fth_status run_enqueue(fth_ctx* c, int64_t nsteps) {
+    fth_status st;
+    const int K = c->opt.steps_per_graph > 0 ? c->opt.steps_per_graph : kDefaultGraphSteps;
+    if (c->d_qt && c->qt_dirty) {
+        if (fth::launch_qt_from_q(static_cast<const float*>(c->d_q[c->step & 1]), c->d_qt, c->n, c->rows_pad, c->R,
+                                  c->stream) != 0)
+            return fail(FTH_EDEVICE, "q split launch failed");
+        c->qt_dirty = false;
+    }
+    if (c->small) return enqueue_small(c, nsteps);
+    int64_t left = nsteps;
+    if (left >= K) {
+        if (!c->gexec || c->gK != K) {
+            st = build_graph(c, K);
+            if (st != FTH_OK) return st;
+        }
+        while (left >= K) {
+            HIP_OK(hipGraphLaunch(c->gexec, c->stream));
+            left -= K;
+        }
+    }
+    if (left > 0) {
+        st = enqueue_chunk(c, int(left));
+        if (st != FTH_OK) return st;
+    }
+    return FTH_OK;
+}
+
+fth_status run_complete(fth_ctx* c, int64_t nsteps) {
+    HIP_OK(hipStreamSynchronize(c->stream));
+    c->step += nsteps;
+    int32_t flag = 0;
+    HIP_OK(hipMemcpy(&flag, c->d_flag, sizeof(flag), hipMemcpyDeviceToHost));
+    if (flag) {
+        c->poisoned = true;
+        return fail(FTH_ENONFINITE, "non-finite state after step %lld (M not SPD or dt too large)", (long long)c->step);
+    }
+    return FTH_OK;
+}
+
+template fth::StepArgs<float> step_args<float>(fth_ctx* c);
+template fth::StepArgs<double> step_args<double>(fth_ctx* c);
+
+}  // namespace host
+}  // namespace fth
+
+using namespace fth::host;
 
 extern "C" {
 
@@ -678,47 +638,15 @@ fth_status fth_run(fth_ctx* c, int64_t nsteps, int32_t replicas) {
         HIP_OK(hipEventRecord(c->ev0, static_cast<hipStream_t>(c->opt.hip_stream)));
         HIP_OK(hipStreamWaitEvent(c->stream, c->ev0, 0));
     }
-    const int K = c->opt.steps_per_graph > 0 ? c->opt.steps_per_graph : kDefaultGraphSteps;
     HIP_OK(hipEventRecord(c->ev0, c->stream));
-    if (c->d_qt && c->qt_dirty) {
-        if (fth::launch_qt_from_q(static_cast<const float*>(c->d_q[c->step & 1]), c->d_qt, c->n, c->rows_pad, c->R,
-                                  c->stream) != 0)
-            return fail(FTH_EDEVICE, "q split launch failed");
-        c->qt_dirty = false;
-    }
-    int64_t left = nsteps;
-    if (c->small) {
-        st = enqueue_small(c, nsteps);
-        if (st != FTH_OK) return st;
-        left = 0;
-    }
-    if (left >= K) {
-        if (!c->gexec || c->gK != K) {
-            st = build_graph(c, K);
-            if (st != FTH_OK) return st;
-        }
-        while (left >= K) {
-            HIP_OK(hipGraphLaunch(c->gexec, c->stream));
-            left -= K;
-        }
-    }
-    if (left > 0) {
-        st = enqueue_chunk(c, int(left));
-        if (st != FTH_OK) return st;
-    }
+    st = run_enqueue(c, nsteps);
+    if (st != FTH_OK) return st;
     HIP_OK(hipEventRecord(c->ev1, c->stream));
     HIP_OK(hipEventSynchronize(c->ev1));
     float ms = 0.f;
     HIP_OK(hipEventElapsedTime(&ms, c->ev0, c->ev1));
     c->last_ms = ms;
-    c->step += nsteps;
-    int32_t flag = 0;
-    HIP_OK(hipMemcpy(&flag, c->d_flag, sizeof(flag), hipMemcpyDeviceToHost));
-    if (flag) {
-        c->poisoned = true;
-        return fail(FTH_ENONFINITE, "non-finite state after step %lld (M not SPD or dt too large)", (long long)c->step);
-    }
-    return FTH_OK;
+    return run_complete(c, nsteps);
 }
 
 int64_t fth_num_outputs(const fth_ctx* c) { return c ? c->n_out() : 0; }

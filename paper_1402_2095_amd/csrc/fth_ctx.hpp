@@ -1,0 +1,123 @@
+// Host-side context of one FTH solve, shared by the C-ABI entry points
+// (fth_api.cpp) and the serving layer (fth_server.cpp).
+#pragma once
+
+#include <hip/hip_runtime.h>
+
+#include <cstdint>
+#include <string>
+#include <vector>
+
+#include "../../include/fth.h"
+#include "fth_internal.h"
+
+struct fth_ctx {
+    // problem
+    int64_t n = 0;
+    int fmt = FTH_CSR;
+    int prec = FTH_FP32;
+    int ns = 0;
+    double h = 0.0;
+    fth_options opt{};
+    int64_t npairs = 0;
+    int64_t nnz = 0;
+    std::vector<double> T, S;
+    // device buffers
+    std::vector<void*> allocs;
+    int64_t* d_row_ptr = nullptr;
+    int32_t* d_col = nullptr;
+    void* d_val = nullptr;
+    void* d_TS = nullptr;
+    int32_t* d_pairs = nullptr;
+    // dense: M padded to rows_pad x rows_pad (bf16 hi/lo, or double), split-K partials, bf16 q split
+    int64_t rows_pad = 0;
+    int ksplit = 1;
+    void* d_m_hi = nullptr;
+    void* d_m_lo = nullptr;
+    void* d_part = nullptr;
+    uint16_t* d_qt = nullptr;
+    bool qt_dirty = true;
+    // small dense systems: persistent single-workgroup kernel, M [n][n] in state precision
+    bool small = false;
+    void* d_msmall = nullptr;
+    size_t small_lds = 0;
+    int small_m_in_lds = 0;
+    std::vector<double> m_host;  // dense M kept until R fixes the path (n <= 4096)
+    bool m_uploaded = false;
+    void* d_q[2] = {nullptr, nullptr};
+    void* d_ps = nullptr;  // [n][ns+1][R]: p then s_1..s_ns per row
+    double* d_acc = nullptr;  // [3][n_out]: blk, s1, s2 (pairs first, then diagonal)
+    int64_t* d_step = nullptr;
+    int32_t* d_flag = nullptr;
+    // schedule
+    int R = 0;
+    int rpt = 0;
+    bool nt = false;  // streaming state access (state larger than the Infinity Cache)
+    int block = 256;
+    hipStream_t stream = nullptr;
+    hipEvent_t ev0 = nullptr, ev1 = nullptr;
+    hipGraphExec_t gexec = nullptr;
+    int gK = 0;
+    int64_t step = 0;
+    bool poisoned = false;
+    double last_ms = 0.0;
+    int device = 0;
+
+    ~fth_ctx() {
+        if (gexec) (void)hipGraphExecDestroy(gexec);
+        if (ev0) (void)hipEventDestroy(ev0);
+        if (ev1) (void)hipEventDestroy(ev1);
+        if (stream) (void)hipStreamSynchronize(stream);
+        for (void* p : allocs) (void)hipFree(p);
+        if (stream) (void)hipStreamDestroy(stream);
+    }
+
+    size_t real_bytes() const { return prec == FTH_FP64 ? 8 : 4; }
+    bool dense() const { return fmt == FTH_DENSE; }
+    bool mfma() const { return dense() && !small; }
+    int64_t q_rows() const { return mfma() ? rows_pad : n; }
+    int64_t n_out() const { return npairs + (opt.acc_diag ? n : 0); }
+
+    hipError_t dalloc(void** p, size_t bytes) {
+        *p = nullptr;
+        if (bytes == 0) bytes = 256;
+        hipError_t e = hipMalloc(p, bytes);
+        if (e == hipSuccess) allocs.push_back(*p);
+        return e;
+    }
+};
+
+namespace fth {
+namespace host {
+
+fth_status fail(fth_status st, const char* fmt, ...);
+extern thread_local std::string g_last_error;
+
+fth_status check_csr(const fth_matrix* M);
+fth_status check_dense(const fth_matrix* M);
+fth_status make_propagator(const fth_gle* g, double dt, std::vector<double>& T, std::vector<double>& S);
+// Allocate (and zero) the state for R replicas; fixes R and the launch shape.
+fth_status ensure_state(fth_ctx* c, int32_t R);
+template <typename Real>
+fth::StepArgs<Real> step_args(fth_ctx* c);
+fth::StepLaunch step_launch(fth_ctx* c);
+// Enqueue K steps (no graph) followed by the step-counter advance.
+fth_status enqueue_chunk(fth_ctx* c, int K);
+// Enqueue K steps of a small dense system (persistent kernel).
+fth_status enqueue_small(fth_ctx* c, int64_t nsteps);
+// Enqueue nsteps steps on the context's stream (graphs, tails, small path).
+fth_status run_enqueue(fth_ctx* c, int64_t nsteps);
+// Wait for the context's stream, count the steps, check the non-finite flag.
+fth_status run_complete(fth_ctx* c, int64_t nsteps);
+
+}  // namespace host
+}  // namespace fth
+
+// Return an fth_status (with a message) from a failed HIP runtime call.
+#define HIP_OK(expr)                                                                          \
+    do {                                                                                      \
+        hipError_t e_ = (expr);                                                               \
+        if (e_ != hipSuccess)                                                                 \
+            return fail(e_ == hipErrorOutOfMemory ? FTH_ENOMEM : FTH_EDEVICE, "%s: %s", #expr, \
+                        hipGetErrorString(e_));                                               \
+    } while (0)

@@ -84,6 +84,13 @@ struct DenseGemmArgs {
     int64_t kslice;       // rows_pad / ksplit
 };
 
+// One entry of the packed multi-request work list.
+struct PackedTile {
+    int32_t slot;   // request slot in the table
+    int32_t pairs;  // 0: row tile, 1: pair tile
+    int64_t index;  // tile index within the request
+};
+
 // Launch wrappers (defined in the .hip files).
 template <typename Real>
 int launch_csr_step(const StepArgs<Real>& a, const StepLaunch& L, int k, void* stream);
@@ -94,6 +101,9 @@ int launch_gemm_f64(const DenseGemmArgs& g, void* stream);
 int launch_split_bf16(const float* m, uint16_t* hi, uint16_t* lo, int64_t count, void* stream);
 int launch_qt_from_q(const float* q, uint16_t* qt, int64_t N, int64_t rows_pad, int32_t R, void* stream);
 int launch_advance(int64_t* step_base, int64_t k, void* stream);
+int launch_packed_csr(const StepArgs<float>* table, const PackedTile* tiles, const int32_t* ntiles, int ns, bool nt,
+                      int grid, int k, void* stream);
+int launch_advance_all(const StepArgs<float>* table, const int32_t* nslots, int64_t K, void* stream);
 // One workgroup advances a small dense system by K steps (and the step counter).
 template <typename Real>
 int launch_small_dense(const StepArgs<Real>& a, const StepLaunch& L, int K, size_t lds_bytes, void* stream);

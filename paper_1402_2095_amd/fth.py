@@ -27,7 +27,10 @@ EXPORTS = [
     "fth_get_accumulators", "fth_get_state", "fth_set_state", "fth_last_run_ms",
     "fth_launches_per_step", "fth_kernel_name", "fth_propagator", "fth_footprint_bytes",
     "fth_destroy", "fth_last_error", "fth_version", "fth_noise_sample", "fth_force",
+    "fth_server_create", "fth_server_submit", "fth_server_tick", "fth_server_poll", "fth_server_result",
+    "fth_server_cancel", "fth_server_clock", "fth_server_stats", "fth_server_destroy",
 ]
+FTH_REQ_QUEUED, FTH_REQ_RUNNING, FTH_REQ_DONE, FTH_REQ_FAILED, FTH_REQ_CANCELLED = 0, 1, 2, 3, 4
 
 
 class FthError(RuntimeError):
@@ -51,6 +54,25 @@ class fth_options(ctypes.Structure):
                 ("burn_in", ctypes.c_int64), ("block_len", ctypes.c_int64), ("acc_diag", ctypes.c_int32),
                 ("replicas", ctypes.c_int32), ("hip_stream", ctypes.c_void_p),
                 ("steps_per_graph", ctypes.c_int32), ("tune", ctypes.c_int32)]
+
+
+class fth_server_options(ctypes.Structure):
+    _fields_ = [("hbm_budget", ctypes.c_size_t), ("steps_per_tick", ctypes.c_int32),
+                ("max_active", ctypes.c_int32), ("min_blocks", ctypes.c_int32)]
+
+
+class fth_request(ctypes.Structure):
+    _fields_ = [("M", fth_matrix), ("gle", fth_gle), ("dt", ctypes.c_double), ("pairs", ctypes.c_void_p),
+                ("npairs", ctypes.c_int64), ("replicas", ctypes.c_int32), ("precision", ctypes.c_int32),
+                ("seed", ctypes.c_uint64), ("stream_id", ctypes.c_uint32), ("burn_in", ctypes.c_int64),
+                ("block_len", ctypes.c_int64), ("target_rel_stderr", ctypes.c_double), ("max_steps", ctypes.c_int64)]
+
+
+class fth_request_info(ctypes.Structure):
+    _fields_ = [("state", ctypes.c_int32), ("status", ctypes.c_int32), ("steps", ctypes.c_int64),
+                ("nblocks", ctypes.c_int64), ("max_rel_stderr", ctypes.c_double), ("t_submit", ctypes.c_double),
+                ("t_start", ctypes.c_double), ("t_finish", ctypes.c_double), ("n_out", ctypes.c_int64),
+                ("replicas", ctypes.c_int32), ("packed", ctypes.c_int32), ("footprint", ctypes.c_size_t)]
 
 
 _lib = None
@@ -83,6 +105,15 @@ def lib():
             "fth_version": (ctypes.c_char_p, []),
             "fth_noise_sample": (i32, [u64, ctypes.c_uint32, i64, P, P, P, P, i32, P, P]),
             "fth_force": (i32, [P, P, P]),
+            "fth_server_create": (i32, [P, P]),
+            "fth_server_submit": (i32, [P, P, P]),
+            "fth_server_tick": (i32, [P]),
+            "fth_server_poll": (i32, [P, u64, P]),
+            "fth_server_result": (i32, [P, u64, P, P, i64]),
+            "fth_server_cancel": (i32, [P, u64]),
+            "fth_server_clock": (dbl, [P]),
+            "fth_server_stats": (i32, [P, P, P, P]),
+            "fth_server_destroy": (i32, [P]),
         }
         for name, (res, args) in sig.items():
             f = getattr(L, name)
@@ -300,6 +331,63 @@ class Solver:
         if self.ctx:
             fth_destroy(self.ctx)
             self.ctx = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+
+class Server:
+    """Request loop over many solves on one GPU (fth_server_*)."""
+
+    def __init__(self, hbm_budget=0, steps_per_tick=0, max_active=0, min_blocks=0):
+        o = fth_server_options(hbm_budget, steps_per_tick, max_active, min_blocks)
+        h = ctypes.c_void_p()
+        _check(lib().fth_server_create(ctypes.byref(o), ctypes.byref(h)))
+        self.h = h
+
+    def submit(self, M, A_p, C_p, dt, pairs, replicas=0, precision=FTH_FP32, seed=0, stream_id=0, burn_in=0,
+               block_len=0, target=1e-2, max_steps=0) -> int:
+        m = _Matrix(M)
+        g, keep = _gle_struct(A_p, C_p)
+        pr = np.ascontiguousarray(pairs, dtype=np.int32).reshape(-1, 2)
+        q = fth_request(m.struct, g, float(dt), pr.ctypes.data, len(pr), int(replicas), int(precision), int(seed),
+                        int(stream_id), int(burn_in), int(block_len), float(target), int(max_steps))
+        rid = ctypes.c_uint64()
+        _check(lib().fth_server_submit(self.h, ctypes.byref(q), ctypes.byref(rid)))
+        return int(rid.value)
+
+    def tick(self):
+        _check(lib().fth_server_tick(self.h))
+
+    def poll(self, rid: int) -> dict:
+        info = fth_request_info()
+        _check(lib().fth_server_poll(self.h, rid, ctypes.byref(info)))
+        return {k: getattr(info, k) for k, _ in fth_request_info._fields_}
+
+    def result(self, rid: int):
+        n = self.poll(rid)["n_out"]
+        est, se = np.zeros(n), np.zeros(n)
+        _check(lib().fth_server_result(self.h, rid, _p(est), _p(se), n))
+        return est, se
+
+    def cancel(self, rid: int):
+        _check(lib().fth_server_cancel(self.h, rid))
+
+    def clock(self) -> float:
+        return float(lib().fth_server_clock(self.h))
+
+    def stats(self):
+        q, r, b = ctypes.c_int64(), ctypes.c_int64(), ctypes.c_size_t()
+        _check(lib().fth_server_stats(self.h, ctypes.byref(q), ctypes.byref(r), ctypes.byref(b)))
+        return int(q.value), int(r.value), int(b.value)
+
+    def close(self):
+        if self.h:
+            lib().fth_server_destroy(self.h)
+            self.h = None
 
     def __del__(self):
         try:
