@@ -122,6 +122,97 @@ def cpu_baseline(M, g, h, R, pairs, budget_s: float):
                       f"warm-up step, {dt:.1f} s, FP64, OpenMP over rows"}
 
 
+def serving_pairs(n: int, seed: int, nd: int = 128, no: int = 128) -> np.ndarray:
+    """128 diagonal elements and 128 off-diagonal pairs among them (so each
+    off-diagonal stderr can be normalised by its two diagonals)."""
+    rng = np.random.default_rng(seed)
+    d = rng.choice(n, size=nd, replace=False)
+    a = rng.integers(0, nd, size=no)
+    b = (a + 1 + rng.integers(0, nd - 1, size=no)) % nd
+    return np.concatenate([np.stack([d, d], 1), np.stack([d[a], d[b]], 1)]).astype(np.int32)
+
+
+def serving(args):
+    """Poisson arrivals of mixed sparse/dense solves, each run to a target
+    relative stderr; reports p50/p99 latency and throughput."""
+    from paper_1402_2095_amd import fth
+    reqs = fi.serving_mix(args.serve_count, args.serve_rate, 5005, n_sparse=(10_000, args.serve_nmax),
+                          n_dense=(512, args.serve_dense_nmax))
+    gles = {"invsqrt": fi.load_gle("invsqrt_ns4"), "fermi": fi.load_gle("fermi_b20_ns4")}
+    prepared = []
+    for r in reqs:
+        if r.kind == "laplacian":
+            side = round(r.n ** (1 / 3))
+            M = fi.laplacian3d_csr(side, 0.1)
+            lmax, n, prec, R = fi.laplacian3d_lambda_max(side, 0.1), M.n, fth.FTH_FP32, 32
+        elif r.kind == "banded":
+            M = fi.banded_spd_csr(r.n, r.seed)
+            lmax, n, prec, R = fi.gershgorin_max(M), M.n, fth.FTH_FP32, 32
+        else:
+            M = fi.dense_ggt(r.n, r.seed)
+            lmax, n, prec, R = fi.power_lambda_max(M.astype(np.float64), iters=30), r.n, fth.FTH_FP32_BF16X3, 64
+        g = gles[r.target]
+        prepared.append(dict(arrival=r.arrival, kind=r.kind, n=n, R=R, target=r.target,
+                             kw=dict(M=M, A_p=g.A_p, C_p=g.C_p, dt=fi.dt_rule(lmax), pairs=serving_pairs(n, r.seed),
+                                     replicas=R, precision=prec, seed=r.seed, stream_id=r.rid + 1, burn_in=1000,
+                                     block_len=200, target=args.serve_target, max_steps=args.serve_max_steps)))
+    srv = fth.Server(steps_per_tick=args.serve_tick)
+    t0 = srv.clock()
+    pending = list(prepared)
+    ids = {}
+    print(f"[serve] {len(prepared)} requests prepared, rate {args.serve_rate}/s, target {args.serve_target}",
+          file=sys.stderr, flush=True)
+    last_report = 0.0
+    while True:
+        now = srv.clock() - t0
+        while pending and pending[0]["arrival"] <= now:
+            p = pending.pop(0)
+            ids[srv.submit(**p["kw"])] = p
+        infos = {i: srv.poll(i) for i in ids}
+        live = [i for i, inf in infos.items() if inf["state"] < fth.FTH_REQ_DONE]
+        if not pending and not live:
+            break
+        if now > args.serve_budget:
+            for i in live:
+                srv.cancel(i)
+            break
+        if not live:
+            time.sleep(max(0.0, min(0.05, pending[0]["arrival"] - now)))
+            continue
+        srv.tick()
+        if now - last_report > 10:
+            last_report = now
+            q, r, b = srv.stats()
+            done = sum(1 for inf in infos.values() if inf["state"] == fth.FTH_REQ_DONE)
+            print(f"[serve] t={now:.0f}s queued={q} running={r} done={done} reserved={b / 1e9:.2f} GB",
+                  file=sys.stderr, flush=True)
+    wall = srv.clock() - t0
+    infos = {i: srv.poll(i) for i in ids}
+    done = [(ids[i], inf) for i, inf in infos.items() if inf["state"] == fth.FTH_REQ_DONE]
+    lat = np.array([inf["t_finish"] - inf["t_submit"] for _, inf in done])
+    work = sum(p["n"] * inf["replicas"] * inf["steps"] for p, inf in done)
+    at_target = sum(1 for _, inf in done if inf["max_rel_stderr"] <= args.serve_target)
+    out = {
+        "metric": "replica*dof*steps/s (serving mix) with p50/p99 latency at fixed stderr",
+        "value": work / wall, "unit": "replica*dof*steps/s", "n_gpus": 1, "steps": None, "warmup": 0,
+        "ms_per_step": None, "higher_is_better": True, "scaling": "weak", "vs_baseline": None, "dtype": "f32",
+        "data": "synthetic",
+        "config": {"workload": "serving mix: Poisson arrivals, 70% sparse (3-D Laplacian / banded SPD, "
+                               f"N in [1e4, {args.serve_nmax:.0e}]), 30% dense (N in [512, {args.serve_dense_nmax}]), "
+                               "Fermi / x^-1/2 50:50, 128 diagonal + 128 off-diagonal estimates each",
+                   "requests": len(prepared), "rate_per_s": args.serve_rate,
+                   "target_rel_stderr": args.serve_target, "steps_per_tick": args.serve_tick,
+                   "scaled": "N ranges and stderr target scaled down from the full mix (see DESIGN)"},
+        "serving": {"completed": len(done), "at_target": at_target, "wall_s": wall,
+                    "p50_latency_s": float(np.percentile(lat, 50)) if len(lat) else None,
+                    "p99_latency_s": float(np.percentile(lat, 99)) if len(lat) else None,
+                    "mean_latency_s": float(lat.mean()) if len(lat) else None,
+                    "requests_per_s": len(done) / wall},
+        "roofline": None, "cpu_baseline": None,
+    }
+    print(json.dumps(out), flush=True)
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -130,10 +221,19 @@ def main():
     ap.add_argument("--workload", default="laplacian64")
     ap.add_argument("--steps-per-graph", type=int, default=64)
     ap.add_argument("--cpu-budget", type=float, default=12.0)
+    ap.add_argument("--no-tune", action="store_true", help="skip the launch-shape autotuner")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--calibrate-copy-mib", type=int, default=0,
                     help="only run a plain elementwise copy (y = -x, float32) of this many MiB, 5 times, "
                          "to scale the FETCH_SIZE / WRITE_SIZE counters")
+    ap.add_argument("--serve-count", type=int, default=24)
+    ap.add_argument("--serve-rate", type=float, default=0.5)
+    ap.add_argument("--serve-target", type=float, default=2e-2)
+    ap.add_argument("--serve-nmax", type=int, default=200_000)
+    ap.add_argument("--serve-dense-nmax", type=int, default=4096)
+    ap.add_argument("--serve-tick", type=int, default=200)
+    ap.add_argument("--serve-max-steps", type=int, default=2_000_000)
+    ap.add_argument("--serve-budget", type=float, default=150.0, help="seconds before the rest is cancelled")
     args = ap.parse_args()
     if args.gpus != 1:
         print("bench.py: this build runs on one GPU only; --gpus must be 1", file=sys.stderr)
@@ -150,6 +250,10 @@ def main():
                           "dispatches": 5}), flush=True)
         return
 
+    if args.workload == "serving":
+        serving(args)
+        return
+
     import torch
     from paper_1402_2095_amd import fth
 
@@ -159,7 +263,8 @@ def main():
     torch.cuda.init()
     stream = torch.cuda.current_stream()
     sol = fth.Solver(M, g.A_p, g.C_p, h, pairs=pairs, replicas=R, precision=prec, seed=2, acc_diag=True,
-                     steps_per_graph=args.steps_per_graph, block_len=100, hip_stream=stream.cuda_stream)
+                     steps_per_graph=args.steps_per_graph, block_len=100, hip_stream=stream.cuda_stream,
+                     tune=not args.no_tune)
     if args.warmup:
         sol.run(args.warmup)
     torch.cuda.synchronize()

@@ -9,7 +9,9 @@
 #include <cstring>
 #include <limits>
 #include <memory>
+#include <map>
 #include <string>
+#include <tuple>
 #include <vector>
 
 #include "fth_ctx.hpp"
@@ -447,6 +449,98 @@ fth_status build_graph(fth_ctx* c, int K) {
     return FTH_OK;
 }
 
+// ------------------------------------------------------------- autotuner
+// Candidate launch shapes of the sparse step: threads per workgroup,
+// replicas per thread, streaming state access.  Each candidate runs a few
+// steps on the live state, which is saved before and restored after, so
+// tuning leaves the trajectory untouched.  The winner is cached per shape
+// key (precision, n, nnz, R, ns).
+struct TuneKey {
+    int prec, ns, R;
+    int64_t n, nnz;
+    bool operator<(const TuneKey& o) const {
+        return std::tie(prec, ns, R, n, nnz) < std::tie(o.prec, o.ns, o.R, o.n, o.nnz);
+    }
+};
+struct TuneChoice {
+    int block, rpt;
+    bool nt;
+    double us;
+};
+std::map<TuneKey, TuneChoice>& tune_cache() {
+    static std::map<TuneKey, TuneChoice> cache;
+    return cache;
+}
+
+fth_status autotune(fth_ctx* c) {
+    if (c->dense() || c->R < 4) return FTH_OK;  // dense GEMM tiles and tiny R have one shape
+    const TuneKey key{c->prec, c->ns, c->R, c->n, c->nnz};
+    auto hit = tune_cache().find(key);
+    if (hit != tune_cache().end()) {
+        c->block = hit->second.block;
+        c->rpt = hit->second.rpt;
+        c->nt = hit->second.nt;
+        c->tuned_us = hit->second.us;
+        return FTH_OK;
+    }
+    // save the state (q pair, ps, accumulators, counter)
+    const size_t rb = c->real_bytes();
+    const size_t qb = size_t(c->q_rows()) * size_t(c->R) * rb;
+    const size_t psb = size_t(c->n) * size_t(c->R) * size_t(c->ns + 1) * rb;
+    const size_t ab = sizeof(double) * size_t(3 * c->n_out());
+    struct Saved {
+        std::vector<void*> p;
+        ~Saved() { for (void* x : p) (void)hipFree(x); }
+    } sv;
+    void* bufs[4] = {c->d_q[0], c->d_q[1], c->d_ps, c->d_acc};
+    const size_t sizes[4] = {qb, qb, psb, std::max<size_t>(ab, 8)};
+    for (int k = 0; k < 4; ++k) {
+        void* x = nullptr;
+        HIP_OK(hipMalloc(&x, sizes[k]));
+        sv.p.push_back(x);
+        HIP_OK(hipMemcpyAsync(x, bufs[k], sizes[k], hipMemcpyDeviceToDevice, c->stream));
+    }
+    int64_t step0 = 0;
+    HIP_OK(hipMemcpy(&step0, c->d_step, sizeof(int64_t), hipMemcpyDeviceToHost));
+    TuneChoice best{c->block, c->rpt, c->nt, 1e30};
+    const int blocks[3] = {64, 128, 256};
+    const int rpts[2] = {4, 8};
+    for (int b : blocks)
+        for (int rp : rpts)
+            for (int ntv = 0; ntv < 2; ++ntv) {
+                if (rp > c->R || c->R / rp > 64 || c->R / rp > b) continue;
+                c->block = b;
+                c->rpt = rp;
+                c->nt = ntv != 0;
+                fth_status st = enqueue_chunk(c, 2);  // warm-up
+                if (st != FTH_OK) return st;
+                HIP_OK(hipEventRecord(c->ev0, c->stream));
+                st = enqueue_chunk(c, 8);
+                if (st != FTH_OK) return st;
+                HIP_OK(hipEventRecord(c->ev1, c->stream));
+                HIP_OK(hipEventSynchronize(c->ev1));
+                float ms = 0.f;
+                HIP_OK(hipEventElapsedTime(&ms, c->ev0, c->ev1));
+                const double us = 1e3 * double(ms) / 8.0;
+                if (us < best.us) best = TuneChoice{b, rp, ntv != 0, us};
+            }
+    // restore
+    for (int k = 0; k < 4; ++k) HIP_OK(hipMemcpyAsync(bufs[k], sv.p[k], sizes[k], hipMemcpyDeviceToDevice, c->stream));
+    HIP_OK(hipMemcpyAsync(c->d_step, &step0, sizeof(int64_t), hipMemcpyHostToDevice, c->stream));
+    HIP_OK(hipMemsetAsync(c->d_flag, 0, sizeof(int32_t), c->stream));
+    HIP_OK(hipStreamSynchronize(c->stream));
+    c->block = best.block;
+    c->rpt = best.rpt;
+    c->nt = best.nt;
+    c->tuned_us = best.us;
+    if (c->gexec) {
+        (void)hipGraphExecDestroy(c->gexec);
+        c->gexec = nullptr;
+    }
+    tune_cache()[key] = best;
+    return FTH_OK;
+}
+
 fth_status run_enqueue(fth_ctx* c, int64_t nsteps) {
     fth_status st;
     const int K = c->opt.steps_per_graph > 0 ? c->opt.steps_per_graph : kDefaultGraphSteps;
@@ -633,6 +727,11 @@ fth_status fth_run(fth_ctx* c, int64_t nsteps, int32_t replicas) {
     if (st != FTH_OK) return st;
     if (nsteps == 0) return FTH_OK;
     HIP_OK(hipSetDevice(c->device));
+    if (c->opt.tune && !c->tuned) {
+        st = autotune(c);
+        if (st != FTH_OK) return st;
+        c->tuned = true;
+    }
     if (c->opt.hip_stream) {
         // order after the caller's stream
         HIP_OK(hipEventRecord(c->ev0, static_cast<hipStream_t>(c->opt.hip_stream)));
@@ -839,8 +938,9 @@ fth_status fth_kernel_name(const fth_ctx* c, char* name, size_t len) {
                       c->prec == FTH_FP64 ? "gemm_f64_kernel" : "gemm_bf16x3_kernel", c->R / 16, c->ksplit,
                       c->prec == FTH_FP64 ? "double" : "float", c->ns, c->rpt, int(c->nt));
     else
-        std::snprintf(name, len, "csr_step_kernel<%s,NS=%d,RPT=%d,NT=%d>", c->prec == FTH_FP64 ? "double" : "float",
-                      c->ns, c->rpt, int(c->nt));
+        std::snprintf(name, len, "csr_step_kernel<%s,NS=%d,RPT=%d,NT=%d> block=%d%s",
+                      c->prec == FTH_FP64 ? "double" : "float", c->ns, c->rpt, int(c->nt), c->block,
+                      c->tuned ? " (autotuned)" : "");
     return FTH_OK;
 }
 

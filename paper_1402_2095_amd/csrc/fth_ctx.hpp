@@ -54,6 +54,8 @@ struct fth_ctx {
     int rpt = 0;
     bool nt = false;  // streaming state access (state larger than the Infinity Cache)
     int block = 256;
+    bool tuned = false;     // launch shape chosen by the autotuner
+    double tuned_us = 0.0;  // its measured step time
     hipStream_t stream = nullptr;
     hipEvent_t ev0 = nullptr, ev1 = nullptr;
     hipGraphExec_t gexec = nullptr;

@@ -215,7 +215,8 @@ fth_status admit(fth_server* s, SrvRequest* r) {
     s->reserved += r->info.footprint;
     r->info.t_start = s->clock();
     r->info.state = FTH_REQ_RUNNING;
-    if (packable(*r)) {
+    // the packed kernel runs 256-thread workgroups with 4 replicas per thread
+    if (packable(*r) && c->rpt == 4 && c->block == 256) {
         r->group = r->gle.ns;
         Group& g = s->groups[r->group];
         g.ns = r->gle.ns;

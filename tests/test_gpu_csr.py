@@ -257,3 +257,22 @@ def test_fp32_estimates_match_closed_form_gh():
     assert np.max(np.abs(z)) < 5.5
     rel = np.abs(est[len(pairs):] / ref[len(pairs):] - 1.0)
     assert np.mean(rel) < 0.01
+
+
+def test_autotuner_keeps_trajectory():
+    """The autotuner picks a launch shape by timing candidates on a saved copy
+    of the state; trajectories are unchanged (replicas per thread only changes
+    the FP64 summation order of the diagonal accumulators)."""
+    M = fi.banded_spd_csr(200_000, 77)
+    g = fi.load_gle("invsqrt_ns4")
+    h = fi.dt_rule(fi.gershgorin_max(M))
+    kw = dict(pairs=fi.random_pairs(M.n, 64, 1), replicas=32, seed=3, acc_diag=True, block_len=10)
+    a = fth.Solver(M, g.A_p, g.C_p, h, tune=True, **kw).run(60)
+    b = fth.Solver(M, g.A_p, g.C_p, h, tune=False, **kw).run(60)
+    print(f"[tune] {a.kernel_name}", flush=True)
+    assert "autotuned" in a.kernel_name
+    for x, y in zip(a.state(), b.state()):
+        assert np.array_equal(x, y)
+    for x, y in zip(a.accumulators()[:3], b.accumulators()[:3]):
+        assert np.allclose(x, y, rtol=1e-12, atol=0)
+    assert a.accumulators()[4] == b.accumulators()[4] == 60
