@@ -120,6 +120,13 @@ typedef struct {
     void* hip_stream;        /* hipStream_t to enqueue on; NULL: own stream */
     int32_t steps_per_graph; /* steps captured per hipGraph launch, 0: default */
     int32_t tune;            /* != 0: autotune the launch shape at first run */
+    int32_t temporal_steps;  /* CSR with half-bandwidth <= 16 and <= 8 entries per row:
+                                steps advanced per temporally blocked launch (3 or 5);
+                                0: the autotuner decides (one-step kernels if not tuning);
+                                -1: never block.  An explicit 3 or 5 on an ineligible
+                                matrix makes fth_run fail with FTH_EUNSUPPORTED. */
+    int32_t temporal_threads; /* threads per blocked workgroup: 256, 512 or 1024 (0: the largest
+                                 allowed for the GLE size and precision) */
 } fth_options;
 
 /* Fill *opt with defaults: seed 0, stream 0, FTH_FP32, burn_in 0,

@@ -33,6 +33,8 @@ fth_status fail(fth_status st, const char* fmt, ...) {
 
 
 constexpr int kDefaultGraphSteps = 64;
+constexpr int kTbMaxSteps = 5;   // longest temporally blocked launch (snapshot depth)
+constexpr int64_t kTbMaxW = 16;  // widest half-bandwidth blocked
 
 bool is_pow2(int64_t x) { return x > 0 && (x & (x - 1)) == 0; }
 int ilog2(int64_t x) {
@@ -419,8 +421,89 @@ fth_status enqueue_small(fth_ctx* c, int64_t nsteps) {
     return FTH_OK;
 }
 
+bool tb_eligible(const fth_ctx* c, int KT, int block) {
+    if (c->dense() || c->band_w < 0 || c->band_w > kTbMaxW || c->max_row_nnz > 8) return false;
+    if (c->R < 4 || c->R > 256) return false;
+    if (KT != 3 && KT != 5) return false;
+    if (block != 256 && block != 512 && block != 1024) return false;
+    if (block > fth::tb_max_block(c->prec == FTH_FP64, c->ns)) return false;
+    const int E = block / (c->R / 4);
+    const int64_t T = E - 2 * int64_t(KT) * c->band_w;
+    return T >= 1 && 2 * T >= E;
+}
+
+fth_status tb_prepare(fth_ctx* c) {
+    if (c->d_ps_alt) return FTH_OK;
+    const size_t rb = c->real_bytes();
+    HIP_OK(c->dalloc(&c->d_ps_alt, size_t(c->n) * size_t(c->R) * size_t(c->ns + 1) * rb));
+    if (c->npairs > 0) {
+        std::vector<int32_t> pairs(size_t(2 * c->npairs));
+        HIP_OK(hipMemcpy(pairs.data(), c->d_pairs, sizeof(int32_t) * pairs.size(), hipMemcpyDeviceToHost));
+        std::vector<int32_t> slot(size_t(c->n), -1);
+        std::vector<int32_t> pslots(pairs.size());
+        int32_t ns = 0;
+        for (size_t k = 0; k < pairs.size(); ++k) {
+            int32_t& sl = slot[size_t(pairs[k])];
+            if (sl < 0) sl = ns++;
+            pslots[k] = sl;
+        }
+        c->tb_nslots = ns;
+        HIP_OK(c->dalloc(reinterpret_cast<void**>(&c->d_pair_slot), sizeof(int32_t) * slot.size()));
+        HIP_OK(hipMemcpy(c->d_pair_slot, slot.data(), sizeof(int32_t) * slot.size(), hipMemcpyHostToDevice));
+        HIP_OK(c->dalloc(reinterpret_cast<void**>(&c->d_pair_slots), sizeof(int32_t) * pslots.size()));
+        HIP_OK(hipMemcpy(c->d_pair_slots, pslots.data(), sizeof(int32_t) * pslots.size(), hipMemcpyHostToDevice));
+        HIP_OK(c->dalloc(&c->d_snap, size_t(kTbMaxSteps) * size_t(ns) * size_t(c->R) * rb));
+    }
+    return FTH_OK;
+}
+
+void tb_release(fth_ctx* c) {
+    c->dfree(c->d_ps_alt);
+    c->dfree(reinterpret_cast<void*&>(c->d_pair_slot));
+    c->dfree(reinterpret_cast<void*&>(c->d_pair_slots));
+    c->dfree(c->d_snap);
+    c->tb_nslots = 0;
+    c->tb_kt = 0;
+}
+
+// Blocked launch j of a chunk: steps [j KT, j KT + KT) of it; (p, s) moves
+// from one buffer to the other, so launches come in pairs.
+template <typename Real>
+fth_status enqueue_tb(fth_ctx* c, int j) {
+    fth::StepArgs<Real> a = step_args<Real>(c);
+    fth::TbArgs<Real> tb{};
+    tb.E = c->tb_block / (c->R / 4);
+    tb.w = int32_t(c->band_w);
+    tb.T = tb.E - 2 * c->tb_kt * tb.w;
+    Real* ps0 = static_cast<Real*>(c->d_ps);
+    Real* ps1 = static_cast<Real*>(c->d_ps_alt);
+    tb.ps_in = (j & 1) ? ps1 : ps0;
+    tb.ps_out = (j & 1) ? ps0 : ps1;
+    tb.pair_slot = c->d_pair_slot;
+    tb.snap = static_cast<Real*>(c->d_snap);
+    tb.nslots = c->tb_nslots;
+    tb.pair_slots = c->d_pair_slots;
+    a.row_tiles = (c->n + tb.T - 1) / tb.T;
+    a.row_tiles_padded = (a.row_tiles + 7) / 8 * 8;
+    const fth::StepLaunch L = step_launch(c);
+    int rc = fth::launch_tb_step<Real>(a, tb, L, c->tb_kt, j * c->tb_kt, c->stream);
+    if (rc == 0) rc = fth::launch_tb_pairs<Real>(a, tb, L, c->tb_kt, j * c->tb_kt, c->stream);
+    if (rc == -2) return fail(FTH_EUNSUPPORTED, "no blocked kernel for ns=%d, KT=%d", c->ns, c->tb_kt);
+    if (rc != 0) return fail(FTH_EDEVICE, "blocked step launch failed (%d): %s", rc, hipGetErrorString(hipGetLastError()));
+    return FTH_OK;
+}
+
 fth_status enqueue_chunk(fth_ctx* c, int K) {
-    for (int k = 0; k < K; ++k) {
+    int k0 = 0;
+    if (c->tb_kt > 0) {
+        const int nl = 2 * (K / (2 * c->tb_kt));
+        for (int j = 0; j < nl; ++j) {
+            fth_status st = c->prec == FTH_FP64 ? enqueue_tb<double>(c, j) : enqueue_tb<float>(c, j);
+            if (st != FTH_OK) return st;
+        }
+        k0 = nl * c->tb_kt;
+    }
+    for (int k = k0; k < K; ++k) {
         fth_status st = enqueue_step(c, k);
         if (st != FTH_OK) return st;
     }
@@ -466,21 +549,46 @@ struct TuneChoice {
     int block, rpt;
     bool nt;
     double us;
+    int tb_kt, tb_block;
 };
 std::map<TuneKey, TuneChoice>& tune_cache() {
     static std::map<TuneKey, TuneChoice> cache;
     return cache;
 }
 
+// Time K steps (enqueued without a graph) on the live state; us per step.
+fth_status time_chunk(fth_ctx* c, int K, double* us) {
+    fth_status st = enqueue_chunk(c, K);  // warm-up
+    if (st != FTH_OK) return st;
+    HIP_OK(hipEventRecord(c->ev0, c->stream));
+    st = enqueue_chunk(c, K);
+    if (st != FTH_OK) return st;
+    HIP_OK(hipEventRecord(c->ev1, c->stream));
+    HIP_OK(hipEventSynchronize(c->ev1));
+    float ms = 0.f;
+    HIP_OK(hipEventElapsedTime(&ms, c->ev0, c->ev1));
+    *us = 1e3 * double(ms) / double(K);
+    return FTH_OK;
+}
+
 fth_status autotune(fth_ctx* c) {
     if (c->dense() || c->R < 4) return FTH_OK;  // dense GEMM tiles and tiny R have one shape
+    if (c->tb_kt > 0) return FTH_OK;            // blocking fixed by the caller
+    const bool try_tb = c->opt.temporal_steps == 0 && (tb_eligible(c, 3, 1024) || tb_eligible(c, 3, 512) ||
+                                                       tb_eligible(c, 3, 256));
+    // (KT = 5 is eligible only where KT = 3 is.)
     const TuneKey key{c->prec, c->ns, c->R, c->n, c->nnz};
     auto hit = tune_cache().find(key);
-    if (hit != tune_cache().end()) {
+    if (hit != tune_cache().end() && (hit->second.tb_kt == 0 || try_tb)) {
         c->block = hit->second.block;
         c->rpt = hit->second.rpt;
         c->nt = hit->second.nt;
         c->tuned_us = hit->second.us;
+        if (hit->second.tb_kt > 0) {
+            c->tb_kt = hit->second.tb_kt;
+            c->tb_block = hit->second.tb_block;
+            return tb_prepare(c);
+        }
         return FTH_OK;
     }
     // save the state (q pair, ps, accumulators, counter)
@@ -502,7 +610,8 @@ fth_status autotune(fth_ctx* c) {
     }
     int64_t step0 = 0;
     HIP_OK(hipMemcpy(&step0, c->d_step, sizeof(int64_t), hipMemcpyDeviceToHost));
-    TuneChoice best{c->block, c->rpt, c->nt, 1e30};
+    TuneChoice best{c->block, c->rpt, c->nt, 1e30, 0, 0};
+    TuneChoice best4 = best;  // best one-step shape with 4 replicas per thread (tail of blocked chunks)
     const int blocks[3] = {64, 128, 256};
     const int rpts[2] = {4, 8};
     for (int b : blocks)
@@ -512,18 +621,32 @@ fth_status autotune(fth_ctx* c) {
                 c->block = b;
                 c->rpt = rp;
                 c->nt = ntv != 0;
-                fth_status st = enqueue_chunk(c, 2);  // warm-up
+                double us = 0.0;
+                fth_status st = time_chunk(c, 8, &us);
                 if (st != FTH_OK) return st;
-                HIP_OK(hipEventRecord(c->ev0, c->stream));
-                st = enqueue_chunk(c, 8);
-                if (st != FTH_OK) return st;
-                HIP_OK(hipEventRecord(c->ev1, c->stream));
-                HIP_OK(hipEventSynchronize(c->ev1));
-                float ms = 0.f;
-                HIP_OK(hipEventElapsedTime(&ms, c->ev0, c->ev1));
-                const double us = 1e3 * double(ms) / 8.0;
-                if (us < best.us) best = TuneChoice{b, rp, ntv != 0, us};
+                if (us < best.us) best = TuneChoice{b, rp, ntv != 0, us, 0, 0};
+                if (rp == 4 && us < best4.us) best4 = TuneChoice{b, rp, ntv != 0, us, 0, 0};
             }
+    if (try_tb && best4.us < 1e30) {
+        fth_status st = tb_prepare(c);
+        if (st != FTH_OK) return st;
+        c->block = best4.block;
+        c->rpt = 4;
+        c->nt = best4.nt;
+        const int kts[2] = {3, 5};
+        const int tbs[3] = {256, 512, 1024};
+        for (int kt : kts)
+            for (int tbb : tbs) {
+                if (!tb_eligible(c, kt, tbb)) continue;
+                c->tb_kt = kt;
+                c->tb_block = tbb;
+                double us = 0.0;
+                st = time_chunk(c, 4 * kt, &us);
+                if (st != FTH_OK) return st;
+                if (us < best.us) best = TuneChoice{best4.block, 4, best4.nt, us, kt, tbb};
+            }
+        c->tb_kt = 0;
+    }
     // restore
     for (int k = 0; k < 4; ++k) HIP_OK(hipMemcpyAsync(bufs[k], sv.p[k], sizes[k], hipMemcpyDeviceToDevice, c->stream));
     HIP_OK(hipMemcpyAsync(c->d_step, &step0, sizeof(int64_t), hipMemcpyHostToDevice, c->stream));
@@ -533,6 +656,9 @@ fth_status autotune(fth_ctx* c) {
     c->rpt = best.rpt;
     c->nt = best.nt;
     c->tuned_us = best.us;
+    c->tb_kt = best.tb_kt;
+    c->tb_block = best.tb_kt > 0 ? best.tb_block : 1024;
+    if (best.tb_kt == 0 && c->d_ps_alt) tb_release(c);
     if (c->gexec) {
         (void)hipGraphExecDestroy(c->gexec);
         c->gexec = nullptr;
@@ -543,7 +669,8 @@ fth_status autotune(fth_ctx* c) {
 
 fth_status run_enqueue(fth_ctx* c, int64_t nsteps) {
     fth_status st;
-    const int K = c->opt.steps_per_graph > 0 ? c->opt.steps_per_graph : kDefaultGraphSteps;
+    int K = c->opt.steps_per_graph > 0 ? c->opt.steps_per_graph : kDefaultGraphSteps;
+    if (c->tb_kt > 0) K = (K + 2 * c->tb_kt - 1) / (2 * c->tb_kt) * (2 * c->tb_kt);  // whole launch pairs
     if (c->d_qt && c->qt_dirty) {
         if (fth::launch_qt_from_q(static_cast<const float*>(c->d_q[c->step & 1]), c->d_qt, c->n, c->rows_pad, c->R,
                                   c->stream) != 0)
@@ -647,6 +774,11 @@ fth_status fth_create(const fth_matrix* M, const fth_gle* gle, double dt, const 
     if (opt.precision < FTH_FP64 || opt.precision > FTH_FP32_BF16X3) return fail(FTH_EINVAL, "unknown precision");
     if (opt.block_len < 1) return fail(FTH_EINVAL, "block_len must be >= 1");
     if (opt.burn_in < 0) return fail(FTH_EINVAL, "burn_in must be >= 0");
+    if (opt.temporal_steps != 0 && opt.temporal_steps != -1 && opt.temporal_steps != 3 && opt.temporal_steps != 5)
+        return fail(FTH_EINVAL, "temporal_steps must be -1, 0, 3 or 5");
+    if (opt.temporal_threads != 0 && opt.temporal_threads != 256 && opt.temporal_threads != 512 &&
+        opt.temporal_threads != 1024)
+        return fail(FTH_EINVAL, "temporal_threads must be 0, 256, 512 or 1024");
     if (npairs < 0 || (npairs > 0 && !pairs)) return fail(FTH_EINVAL, "invalid pair list");
     for (int64_t k = 0; k < 2 * npairs; ++k)
         if (pairs[k] < 0 || pairs[k] >= M->n) return fail(FTH_EINVAL, "pair index out of range at %lld", (long long)k);
@@ -688,6 +820,14 @@ fth_status fth_create(const fth_matrix* M, const fth_gle* gle, double dt, const 
             c->m_uploaded = true;
         }
     } else {
+        int64_t w = 0, maxnz = 0;
+        for (int64_t i = 0; i < M->n; ++i) {
+            maxnz = std::max(maxnz, M->row_ptr[i + 1] - M->row_ptr[i]);
+            for (int64_t k = M->row_ptr[i]; k < M->row_ptr[i + 1]; ++k)
+                w = std::max(w, std::abs(int64_t(M->col[k]) - i));
+        }
+        c->band_w = w;
+        c->max_row_nnz = int(std::min<int64_t>(maxnz, 1 << 30));
         HIP_OK(c->dalloc(reinterpret_cast<void**>(&c->d_row_ptr), sizeof(int64_t) * size_t(M->n + 1)));
         HIP_OK(hipMemcpy(c->d_row_ptr, M->row_ptr, sizeof(int64_t) * size_t(M->n + 1), hipMemcpyHostToDevice));
         HIP_OK(c->dalloc(reinterpret_cast<void**>(&c->d_col), sizeof(int32_t) * size_t(M->nnz)));
@@ -727,6 +867,20 @@ fth_status fth_run(fth_ctx* c, int64_t nsteps, int32_t replicas) {
     if (st != FTH_OK) return st;
     if (nsteps == 0) return FTH_OK;
     HIP_OK(hipSetDevice(c->device));
+    if (c->opt.temporal_steps > 0 && c->tb_kt == 0) {
+        const int tbb = c->opt.temporal_threads > 0 ? c->opt.temporal_threads
+                                                    : fth::tb_max_block(c->prec == FTH_FP64, c->ns);
+        if (!tb_eligible(c, c->opt.temporal_steps, tbb))
+            return fail(FTH_EUNSUPPORTED,
+                        "temporal blocking needs CSR with half-bandwidth <= %lld (%lld), <= 8 entries per row (%d), "
+                        "4 <= R <= 256 and at least half of each workgroup's rows as output",
+                        (long long)kTbMaxW, (long long)c->band_w, c->max_row_nnz);
+        c->tb_kt = c->opt.temporal_steps;
+        c->tb_block = tbb;
+        c->rpt = 4;
+        st = tb_prepare(c);
+        if (st != FTH_OK) return st;
+    }
     if (c->opt.tune && !c->tuned) {
         st = autotune(c);
         if (st != FTH_OK) return st;
@@ -937,6 +1091,10 @@ fth_status fth_kernel_name(const fth_ctx* c, char* name, size_t len) {
         std::snprintf(name, len, "%s<RT=%d,ksplit=%d> + dense_epilogue_kernel<%s,NS=%d,RPT=%d,NT=%d>",
                       c->prec == FTH_FP64 ? "gemm_f64_kernel" : "gemm_bf16x3_kernel", c->R / 16, c->ksplit,
                       c->prec == FTH_FP64 ? "double" : "float", c->ns, c->rpt, int(c->nt));
+    else if (c->tb_kt > 0)
+        std::snprintf(name, len, "tb_step_kernel<%s,NS=%d,RPT=4,KT=%d> block=%d (+ csr_step_kernel block=%d tail)%s",
+                      c->prec == FTH_FP64 ? "double" : "float", c->ns, c->tb_kt, c->tb_block, c->block,
+                      c->tuned ? " (autotuned)" : "");
     else
         std::snprintf(name, len, "csr_step_kernel<%s,NS=%d,RPT=%d,NT=%d> block=%d%s",
                       c->prec == FTH_FP64 ? "double" : "float", c->ns, c->rpt, int(c->nt), c->block,

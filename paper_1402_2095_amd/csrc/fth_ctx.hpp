@@ -49,6 +49,16 @@ struct fth_ctx {
     double* d_acc = nullptr;  // [3][n_out]: blk, s1, s2 (pairs first, then diagonal)
     int64_t* d_step = nullptr;
     int32_t* d_flag = nullptr;
+    // temporal blocking of narrow-band CSR systems
+    int64_t band_w = -1;   // half-bandwidth max |j - i| of the CSR pattern
+    int max_row_nnz = 0;   // longest CSR row
+    int tb_kt = 0;         // steps per blocked launch, 0: one-step kernels
+    int tb_block = 1024;   // threads per blocked workgroup
+    void* d_ps_alt = nullptr;          // second (p, s) buffer: blocked launches ping-pong
+    int32_t* d_pair_slot = nullptr;    // [n]: snapshot slot of a row in a pair, or -1
+    int32_t* d_pair_slots = nullptr;   // [npairs][2]
+    void* d_snap = nullptr;            // [kTbMaxSteps][nslots][R]
+    int64_t tb_nslots = 0;
     // schedule
     int R = 0;
     int rpt = 0;
@@ -80,6 +90,16 @@ struct fth_ctx {
     int64_t q_rows() const { return mfma() ? rows_pad : n; }
     int64_t n_out() const { return npairs + (opt.acc_diag ? n : 0); }
 
+    void dfree(void*& p) {
+        for (auto it = allocs.begin(); it != allocs.end(); ++it)
+            if (*it == p) {
+                allocs.erase(it);
+                (void)hipFree(p);
+                break;
+            }
+        p = nullptr;
+    }
+
     hipError_t dalloc(void** p, size_t bytes) {
         *p = nullptr;
         if (bytes == 0) bytes = 256;
@@ -105,6 +125,10 @@ fth::StepArgs<Real> step_args(fth_ctx* c);
 fth::StepLaunch step_launch(fth_ctx* c);
 // Enqueue K steps (no graph) followed by the step-counter advance.
 fth_status enqueue_chunk(fth_ctx* c, int K);
+// Temporal blocking: whether the CSR system qualifies for KT steps per launch
+// with the given workgroup size, and the device buffers it needs.
+bool tb_eligible(const fth_ctx* c, int KT, int block);
+fth_status tb_prepare(fth_ctx* c);
 // Enqueue K steps of a small dense system (persistent kernel).
 fth_status enqueue_small(fth_ctx* c, int64_t nsteps);
 // Enqueue nsteps steps on the context's stream (graphs, tails, small path).

@@ -84,6 +84,27 @@ struct DenseGemmArgs {
     int64_t kslice;       // rows_pad / ksplit
 };
 
+// Largest workgroup of the temporally blocked step: a row's (p, s) and CSR
+// entries stay in registers for the whole launch, so larger NS (and FP64)
+// need the register file of fewer threads.
+constexpr int tb_max_block(bool f64, int ns) {
+    return f64 ? (ns <= 1 ? 1024 : ns <= 4 ? 512 : 256) : (ns <= 5 ? 1024 : 512);
+}
+
+// Extra arguments of the temporally blocked sparse step.
+template <typename Real>
+struct TbArgs {
+    int32_t E;                 // extended rows per workgroup
+    int32_t T;                 // output rows per workgroup
+    int32_t w;                 // half-bandwidth of M
+    const Real* ps_in;         // (p, s) before the launch
+    Real* ps_out;              // (p, s) after the launch (the other buffer)
+    const int32_t* pair_slot;  // [N]: snapshot slot of a row used by a pair, or -1
+    Real* snap;                // [KT][nslots][R]: q of pair rows at each step
+    int64_t nslots;
+    const int32_t* pair_slots; // [npairs][2]: snapshot slots of each pair's rows
+};
+
 // One entry of the packed multi-request work list.
 struct PackedTile {
     int32_t slot;   // request slot in the table
@@ -101,6 +122,11 @@ int launch_gemm_f64(const DenseGemmArgs& g, void* stream);
 int launch_split_bf16(const float* m, uint16_t* hi, uint16_t* lo, int64_t count, void* stream);
 int launch_qt_from_q(const float* q, uint16_t* qt, int64_t N, int64_t rows_pad, int32_t R, void* stream);
 int launch_advance(int64_t* step_base, int64_t k, void* stream);
+// Temporally blocked step: one launch advances KT steps (KT odd); pairs follow.
+template <typename Real>
+int launch_tb_step(const StepArgs<Real>& a, const TbArgs<Real>& tb, const StepLaunch& L, int KT, int k, void* stream);
+template <typename Real>
+int launch_tb_pairs(const StepArgs<Real>& a, const TbArgs<Real>& tb, const StepLaunch& L, int KT, int k, void* stream);
 int launch_packed_csr(const StepArgs<float>* table, const PackedTile* tiles, const int32_t* ntiles, int ns, bool nt,
                       int grid, int k, void* stream);
 int launch_advance_all(const StepArgs<float>* table, const int32_t* nslots, int64_t K, void* stream);
