@@ -29,6 +29,18 @@ sys.path.insert(0, ROOT)
 import fth_inputs as fi  # noqa: E402
 
 HBM_PEAK_GBS = 8000.0
+# Full-rate 32-bit VALU lane operations per second: 256 CUs x 4 SIMDs x 32
+# lanes x 2.4 GHz (the FP32 vector peak of 157.3 TFLOP/s counts an FMA as 2).
+ALU_PEAK_GOPS = 256 * 4 * 32 * 2.4
+PROFILE_DIR = os.path.join(ROOT, "profiles")
+CSRC = os.path.join(ROOT, "paper_1402_2095_amd", "csrc")
+# Device sources of each step form; a committed traffic figure is used only
+# while their hash is unchanged.
+KERNEL_SOURCES = {
+    "csr": ["csr_step.hpp", "csr_step_f32.hip", "csr_step_f64.hip", "row_update.hpp", "noise.hpp"],
+    "tb": ["tb_step.hpp", "tb_step.hip", "row_update.hpp", "noise.hpp"],
+    "dense": ["dense.hpp", "dense_f32.hip", "dense_f64.hip", "row_update.hpp", "noise.hpp"],
+}
 
 
 def workload(name: str):
@@ -85,19 +97,164 @@ def dense_roofline(M, ns: int, R: int, npairs: int, prec: int, per_step_s: float
     return float(mbytes + state + part), flops
 
 
-def algorithmic_bytes(M, ns: int, R: int, npairs: int, prec: int) -> float:
-    """Bytes one step must move at minimum: state q (read q_n, write q_{n+1}),
-    p and s_1..s_ns read and written; the CSR arrays once (row_ptr 8 B, col 4
-    B, value per nonzero); the diagonal block accumulator read and written
-    (FP64); each pair's two q rows and its accumulator."""
+def algorithmic_bytes(M, ns: int, R: int, npairs: int, prec: int, steps_per_launch: int = 1) -> float:
+    """Bytes one launch must move at minimum: state q (read q_n, write
+    q_{n+k}), p and s_1..s_ns read and written; the CSR arrays once (row_ptr
+    8 B, col 4 B, value per nonzero); the diagonal block accumulator read and
+    written (FP64); per step, each pair's two q rows and its accumulator.  A
+    blocked launch advancing k steps moves the state and the matrix once."""
     from paper_1402_2095_amd import fth
     b = 8 if prec == fth.FTH_FP64 else 4
     n = M.n
     state = 2 * (ns + 2) * b * n * R
     csr = (n + 1) * 8 + M.nnz * (4 + b)
     diag = 16 * n
-    pairs = npairs * (2 * R * b + 16 + 8)
+    pairs = steps_per_launch * npairs * (2 * R * b + 16 + 8)
     return float(state + csr + diag + pairs)
+
+
+def alu_ops_per_row_step(ns: int, nnz_row: float) -> float:
+    """Full-rate-equivalent VALU lane operations one replica of one row needs
+    per step (half-rate operations count 2, quarter-rate 4):
+      Philox4x32-10, per component, shared by 4 replicas: 10 rounds of two
+        32x32->64 multiplies (2 each) and four XORs            -> 20 / replica
+      uniform from a word: shift, convert (2), FMA               -> 4
+      Box-Muller, per pair of normals: log2, sqrt, sin, cos (4 each) and
+        three multiplies                                         -> 9.5 / normal
+      force: one FMA per nonzero; OU update: (ns+1)^2 + (ns+1)(ns+2)/2 FMAs,
+      two kicks and the drift; diagonal accumulator: convert and FP64 FMA (2 each)."""
+    d = ns + 1
+    noise = d * (20.0 + 4.0 + 9.5)
+    return noise + nnz_row + d * d + d * (d + 1) / 2 + 3 + 4
+
+
+def source_hash(kind: str) -> str:
+    import hashlib
+    hsh = hashlib.sha256()
+    for f in KERNEL_SOURCES[kind]:
+        with open(os.path.join(CSRC, f), "rb") as fh:
+            hsh.update(fh.read())
+    return hsh.hexdigest()
+
+
+def unit_of(kernel_name: str):
+    """The kernels of one timed unit, as rocprofv3 names them, its kind and
+    the steps it covers, from the library's description of the step."""
+    import re
+    m = re.search(r"tb_step_kernel<(\w+),NS=(\d+),RPT=4,KT=(\d+)>", kernel_name)
+    if m:
+        real, ns, kt = m.group(1), m.group(2), int(m.group(3))
+        return "tb", [f"tb_step_kernel<{real}, {ns}, 4, {kt}>", f"tb_pairs_kernel<{real}, 4, {kt}>"], kt
+    m = re.search(r"csr_step_kernel<(\w+),NS=(\d+),RPT=(\d+),NT=(\d)>", kernel_name)
+    if m:
+        real, ns, rpt, nt = m.groups()
+        return "csr", [f"csr_step_kernel<{real}, {ns}, {rpt}, {'true' if nt == '1' else 'false'}>"], 1
+    m = re.search(r"(gemm_bf16x3_kernel|gemm_f64_kernel)<RT=(\d+),ksplit=\d+> \+ "
+                  r"dense_epilogue_kernel<(\w+),NS=(\d+),RPT=(\d+),NT=(\d)>", kernel_name)
+    if m:
+        gemm, rt, real, ns, rpt, nt = m.groups()
+        return "dense", [f"{gemm}<{rt}>", f"dense_epilogue_kernel<{real}, {ns}, {rpt}, "
+                                          f"{'true' if nt == '1' else 'false'}>"], 1
+    return None, [], 1
+
+
+def committed_traffic(workload_name: str, kernel_name: str):
+    """HBM bytes per unit from the committed rocprofv3 summary of this
+    workload, if it covers the kernels now selected and their sources are
+    unchanged since the counters were taken; else None."""
+    kind, names, _ = unit_of(kernel_name)
+    if kind is None or not os.path.isdir(PROFILE_DIR):
+        return None
+    for f in sorted(os.listdir(PROFILE_DIR)):
+        if not f.endswith(f"_{workload_name}.txt"):
+            continue
+        fields = {}
+        with open(os.path.join(PROFILE_DIR, f)) as fh:
+            for line in fh:
+                if ": " in line and not line.startswith(" "):
+                    k, v = line.rstrip("\n").split(": ", 1)
+                    fields[k] = v
+        if fields.get("unit_kernels") == " + ".join(names) and fields.get("source_sha256") == source_hash(kind):
+            try:
+                return float(fields["traffic_bytes_per_unit"])
+            except (KeyError, ValueError):
+                return None
+    return None
+
+
+def profile_summary(d: str, workload_name: str) -> str:
+    """Condense one rocprofv3 profiling pass of a workload (kernel trace with
+    --stats, a FETCH_SIZE and a WRITE_SIZE counter run, and the same two
+    counters on a plain 1 GiB float32 copy for scale) into the text kept
+    under profiles/.  Layout of d: kt/ (kernel trace, -o kt), kt.log (the
+    bench line printed under the trace), fetch/ and write/ (-o pmc),
+    fetch_copy/ and write_copy/ (-o pmc), commands.txt."""
+    import csv
+    import statistics
+    from collections import defaultdict
+
+    def pmc(sub):
+        vals = defaultdict(list)
+        with open(os.path.join(d, sub, "pmc_counter_collection.csv")) as fh:
+            for row in csv.DictReader(fh):
+                vals[row["Kernel_Name"]].append(float(row["Counter_Value"]))
+        return vals
+
+    with open(os.path.join(d, "kt.log")) as fh:
+        bench_line = json.loads([ln for ln in fh if ln.startswith("{")][-1])
+    kname = bench_line["config"]["kernel"]
+    kind, names, unit_steps = unit_of(kname)
+    with open(os.path.join(d, "kt", "kt_kernel_stats.csv")) as fh:
+        stats = list(csv.DictReader(fh))
+    cf, cw = pmc("fetch_copy"), pmc("write_copy")
+    copy_key = max((k for k in cf if "elementwise" in k), key=lambda k: len(cf[k]))
+    copy_bytes = float(1 << 30)
+    fscale = copy_bytes / 1024.0 / statistics.median(cf[copy_key])
+    wscale = copy_bytes / 1024.0 / statistics.median(cw[copy_key])
+    fe, wr = pmc("fetch"), pmc("write")
+    lines = [f"rocprofv3 summary: {kname}",
+             f"workload: {workload_name} ({bench_line['config']['workload']}, R={bench_line['config']['replicas']})",
+             f"unit of work: {bench_line['roofline']['unit_of_work']}", "",
+             "commands (from the repository root on one MI355X, after cd /tmp && export TMPDIR=/tmp;",
+             "           REPO is the repository root, OUT the output directory):"]
+    with open(os.path.join(d, "commands.txt")) as fh:
+        lines += ["  " + ln.rstrip() for ln in fh if ln.strip()]
+    lines += ["", "kernel trace statistics (top 8 by total time):",
+              f"  {'kernel':<72} {'calls':>6} {'avg us':>9} {'min us':>9} {'max us':>9} {'%':>6}"]
+    for r in stats[:8]:
+        lines.append(f"  {r['Name'].replace('void fth::dev::', '')[:72]:<72} {r['Calls']:>6} "
+                     f"{float(r['AverageNs']) / 1e3:9.2f} {float(r['MinNs']) / 1e3:9.2f} "
+                     f"{float(r['MaxNs']) / 1e3:9.2f} {float(r['Percentage']):6.2f}")
+    lines += ["", f"counter scale from the copy kernel ({copy_key.split('(')[0][:60]}..., 1 GiB read + 1 GiB written):",
+              f"  FETCH_SIZE x {fscale:.3f}, WRITE_SIZE x {wscale:.3f}", "",
+              "per dispatch of the unit's kernels (median over dispatches):"]
+    avg_ns, fetch_b, write_b = 0.0, 0.0, 0.0
+    for nm in names:
+        st = [r for r in stats if nm in r["Name"]]
+        kf = [k for k in fe if nm in k]
+        kw = [k for k in wr if nm in k]
+        a = float(st[0]["AverageNs"]) if st else float("nan")
+        f_raw = statistics.median(fe[kf[0]]) if kf else float("nan")
+        w_raw = statistics.median(wr[kw[0]]) if kw else float("nan")
+        avg_ns += a
+        fetch_b += f_raw * 1024 * fscale
+        write_b += w_raw * 1024 * wscale
+        lines.append(f"  {nm}: avg {a / 1e3:.2f} us, FETCH_SIZE {f_raw:.0f} KiB -> {f_raw * 1024 * fscale / 1e6:.1f} MB, "
+                     f"WRITE_SIZE {w_raw:.0f} KiB -> {w_raw * 1024 * wscale / 1e6:.1f} MB")
+    roof = bench_line["roofline"]
+    lines += ["", f"unit totals: avg {avg_ns / 1e3:.2f} us (bench, HIP events: {roof['avg_unit_us']:.2f} us), "
+                  f"HBM traffic {(fetch_b + write_b) / 1e6:.1f} MB "
+                  f"(algorithmic {roof['algorithmic_bytes_per_unit'] / 1e6:.1f} MB)",
+              f"measured traffic rate {(fetch_b + write_b) / avg_ns:.0f} GB/s; roofline in the bench line: "
+              f"bound {roof['bound']}, frac {roof['frac']:.3f}", "",
+              "bench line printed under the trace:", "  " + json.dumps(bench_line), "",
+              f"unit_kernels: {' + '.join(names)}",
+              f"source_sha256: {source_hash(kind)}",
+              f"avg_unit_ns: {avg_ns:.1f}",
+              f"fetch_bytes_per_unit: {fetch_b:.6e}",
+              f"write_bytes_per_unit: {write_b:.6e}",
+              f"traffic_bytes_per_unit: {fetch_b + write_b:.6e}"]
+    return "\n".join(lines) + "\n"
 
 
 def cpu_baseline(M, g, h, R, pairs, budget_s: float):
@@ -234,7 +391,18 @@ def main():
     ap.add_argument("--serve-tick", type=int, default=200)
     ap.add_argument("--serve-max-steps", type=int, default=2_000_000)
     ap.add_argument("--serve-budget", type=float, default=150.0, help="seconds before the rest is cancelled")
+    ap.add_argument("--profile-summary", default=None, metavar="DIR",
+                    help="write profiles/<kernel>_<workload>.txt from a rocprofv3 pass stored in DIR and exit")
     args = ap.parse_args()
+    if args.profile_summary:
+        text = profile_summary(args.profile_summary, args.workload)
+        kind, names, _ = unit_of(text.splitlines()[0])
+        base = names[0].split("<")[0] if names else "kernel"
+        os.makedirs(PROFILE_DIR, exist_ok=True)
+        with open(os.path.join(PROFILE_DIR, f"{base}_{args.workload}.txt"), "w") as fh:
+            fh.write(text)
+        print(text)
+        return
     if args.gpus != 1:
         print("bench.py: this build runs on one GPU only; --gpus must be 1", file=sys.stderr)
         sys.exit(2)
@@ -273,20 +441,44 @@ def main():
     torch.cuda.synchronize()
     wall = time.perf_counter() - t0
     gpu_ms = sol.last_run_ms
-    launches = steps * fth.fth_launches_per_step(sol.ctx)
-    per_launch_s = gpu_ms * 1e-3 / launches
-    dense = isinstance(M, np.ndarray)
-    if dense:
-        # both launches of a step are timed together: the step is the unit
-        per_launch_s = gpu_ms * 1e-3 / steps
-        abytes, flops = dense_roofline(M, g.ns, R, len(pairs), prec, per_launch_s)
-    else:
-        abytes = algorithmic_bytes(M, g.ns, R, len(pairs), prec)
-    achieved = abytes / per_launch_s / 1e9
     est, se, nsamp = sol.read()
     assert np.all(np.isfinite(est)), "non-finite estimates"
-
+    dense = isinstance(M, np.ndarray)
     n = M.shape[0] if dense else M.n
+    kind, unit_kernels, unit_steps = unit_of(sol.kernel_name)
+    units = steps / unit_steps
+    per_unit_s = gpu_ms * 1e-3 / units   # HIP events around the timed run, on the library's stream
+    traffic = committed_traffic(args.workload, sol.kernel_name)
+    alu_ops = n * R * unit_steps * alu_ops_per_row_step(g.ns, 0.0 if dense else M.nnz / M.n)
+    alu = {"achieved": alu_ops / per_unit_s / 1e9, "peak": ALU_PEAK_GOPS, "unit": "Gop/s",
+           "frac": alu_ops / per_unit_s / 1e9 / ALU_PEAK_GOPS}
+    if dense:
+        abytes, flops = dense_roofline(M, g.ns, R, len(pairs), prec, per_unit_s)
+    elif kind == "tb":
+        abytes = algorithmic_bytes(M, g.ns, R, len(pairs), prec, steps_per_launch=unit_steps)
+    else:
+        abytes = algorithmic_bytes(M, g.ns, R, len(pairs), prec)
+    achieved = abytes / per_unit_s / 1e9
+    hbm = {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
+           "frac": achieved / HBM_PEAK_GBS, "traffic": traffic}
+    unit_desc = {"csr": "one step (one step-kernel launch)",
+                 "tb": f"one blocked launch = {unit_steps} steps (step kernel + pair kernel)",
+                 "dense": "one step (GEMM + epilogue launches)"}.get(kind, "one step")
+    if kind == "tb":
+        # several steps per launch with the state in registers and LDS: VALU-limited
+        roof = {"bound": "alu", **{k: alu[k] for k in ("achieved", "peak", "unit", "frac")}, "traffic": traffic,
+                "hbm": {k: hbm[k] for k in ("achieved", "peak", "unit", "frac")}}
+    else:
+        roof = dict(hbm)
+        roof["alu"] = alu
+    roof.update({"unit_of_work": unit_desc, "kernels": unit_kernels, "algorithmic_bytes_per_unit": abytes,
+                 "alu_ops_per_unit": alu_ops, "avg_unit_us": per_unit_s * 1e6})
+    if dense:
+        mfma_peak = 78.6 if prec == fth.FTH_FP64 else 2500.0
+        tf = flops * (3 if prec == fth.FTH_FP32_BF16X3 else 1) / per_unit_s / 1e12
+        roof["mfma"] = {"issued_tflops": tf, "peak_tflops": mfma_peak, "frac": tf / mfma_peak,
+                        "algorithmic_tflops": flops / per_unit_s / 1e12}
+
     value = n * R * steps / wall
     out = {
         "metric": "replica*dof*steps/s",
@@ -303,17 +495,9 @@ def main():
         "data": "synthetic",
         "config": dict(desc, precision="fp64" if prec == fth.FTH_FP64 else "fp32 state, fp64 accumulators",
                        steps_per_graph=args.steps_per_graph, kernel=sol.kernel_name),
-        "roofline": {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
-                     "frac": achieved / HBM_PEAK_GBS, "traffic": None,
-                     "algorithmic_bytes_per_launch": abytes, "avg_launch_us": per_launch_s * 1e6},
+        "roofline": roof,
         "cpu_baseline": None,
     }
-    if dense:
-        mfma_peak = 78.6 if prec == fth.FTH_FP64 else 2500.0
-        tf = flops * (3 if prec == fth.FTH_FP32_BF16X3 else 1) / per_launch_s / 1e12
-        out["roofline"]["mfma"] = {"issued_tflops": tf, "peak_tflops": mfma_peak, "frac": tf / mfma_peak,
-                                   "algorithmic_tflops": flops / per_launch_s / 1e12}
-        out["roofline"]["note"] = "one unit = one step (GEMM + epilogue launches)"
     if not args.no_cpu_baseline:
         out["cpu_baseline"] = cpu_baseline(M, g, h, R, pairs, args.cpu_budget)
     sol.close()
