@@ -346,6 +346,10 @@ def serving(args):
     wall = srv.clock() - t0
     infos = {i: srv.poll(i) for i in ids}
     done = [(ids[i], inf) for i, inf in infos.items() if inf["state"] == fth.FTH_REQ_DONE]
+    not_done = [{"kind": ids[i]["kind"], "n": ids[i]["n"], "state": inf["state"], "status": inf["status"],
+                 "steps": inf["steps"]} for i, inf in infos.items() if inf["state"] != fth.FTH_REQ_DONE]
+    for nd in not_done:
+        print(f"[serve] not completed: {nd}", file=sys.stderr, flush=True)
     lat = np.array([inf["t_finish"] - inf["t_submit"] for _, inf in done])
     work = sum(p["n"] * inf["replicas"] * inf["steps"] for p, inf in done)
     at_target = sum(1 for _, inf in done if inf["max_rel_stderr"] <= args.serve_target)
@@ -360,7 +364,7 @@ def serving(args):
                    "requests": len(prepared), "rate_per_s": args.serve_rate,
                    "target_rel_stderr": args.serve_target, "steps_per_tick": args.serve_tick,
                    "scaled": "N ranges and stderr target scaled down from the full mix (see DESIGN)"},
-        "serving": {"completed": len(done), "at_target": at_target, "wall_s": wall,
+        "serving": {"completed": len(done), "not_completed": not_done, "at_target": at_target, "wall_s": wall,
                     "p50_latency_s": float(np.percentile(lat, 50)) if len(lat) else None,
                     "p99_latency_s": float(np.percentile(lat, 99)) if len(lat) else None,
                     "mean_latency_s": float(lat.mean()) if len(lat) else None,
