@@ -292,16 +292,19 @@ fth_status ensure_state(fth_ctx* c, int32_t R) {
     c->R = R;
     c->rpt = rpt;
     const size_t rb = c->real_bytes();
+    // (p, s) row groups: one component of a group fills at least a 128-byte line
+    c->ps_lg = R * int(rb) >= 128 ? 0 : ilog2(128 / (R * int(rb)));
+    c->ps_rows = (c->n + (int64_t(1) << c->ps_lg) - 1) >> c->ps_lg << c->ps_lg;
     const size_t qst = size_t(c->q_rows()) * size_t(R) * rb;
     const size_t st = size_t(c->n) * size_t(R) * rb;
     // State streamed once per step: bypass L2/MALL when it cannot stay resident.
     c->nt = st * size_t(c->ns + 3) > (size_t(128) << 20);
     HIP_OK(c->dalloc(&c->d_q[0], qst));
     HIP_OK(c->dalloc(&c->d_q[1], qst));
-    HIP_OK(c->dalloc(&c->d_ps, st * size_t(c->ns + 1)));
+    HIP_OK(c->dalloc(&c->d_ps, c->ps_bytes()));
     HIP_OK(hipMemsetAsync(c->d_q[0], 0, qst, c->stream));
     HIP_OK(hipMemsetAsync(c->d_q[1], 0, qst, c->stream));
-    HIP_OK(hipMemsetAsync(c->d_ps, 0, st * size_t(c->ns + 1), c->stream));
+    HIP_OK(hipMemsetAsync(c->d_ps, 0, c->ps_bytes(), c->stream));
     if (c->mfma()) {
         const size_t pb = size_t(c->ksplit) * size_t(c->rows_pad) * size_t(R) * rb;
         HIP_OK(c->dalloc(&c->d_part, pb));
@@ -332,6 +335,7 @@ fth::StepArgs<Real> step_args(fth_ctx* c) {
     a.q0 = static_cast<Real*>(c->d_q[0]);
     a.q1 = static_cast<Real*>(c->d_q[1]);
     a.ps = static_cast<Real*>(c->d_ps);
+    a.ps_lg = c->ps_lg;
     a.TS = static_cast<const Real*>(c->d_TS);
     a.h = Real(c->h);
     a.hh = Real(0.5 * c->h);
@@ -435,7 +439,7 @@ bool tb_eligible(const fth_ctx* c, int KT, int block) {
 fth_status tb_prepare(fth_ctx* c) {
     if (c->d_ps_alt) return FTH_OK;
     const size_t rb = c->real_bytes();
-    HIP_OK(c->dalloc(&c->d_ps_alt, size_t(c->n) * size_t(c->R) * size_t(c->ns + 1) * rb));
+    HIP_OK(c->dalloc(&c->d_ps_alt, c->ps_bytes()));
     if (c->npairs > 0) {
         std::vector<int32_t> pairs(size_t(2 * c->npairs));
         HIP_OK(hipMemcpy(pairs.data(), c->d_pairs, sizeof(int32_t) * pairs.size(), hipMemcpyDeviceToHost));
@@ -594,7 +598,7 @@ fth_status autotune(fth_ctx* c) {
     // save the state (q pair, ps, accumulators, counter)
     const size_t rb = c->real_bytes();
     const size_t qb = size_t(c->q_rows()) * size_t(c->R) * rb;
-    const size_t psb = size_t(c->n) * size_t(c->R) * size_t(c->ns + 1) * rb;
+    const size_t psb = c->ps_bytes();
     const size_t ab = sizeof(double) * size_t(3 * c->n_out());
     struct Saved {
         std::vector<void*> p;
@@ -742,15 +746,18 @@ size_t fth_footprint_bytes(const fth_matrix* M, int32_t ns, int32_t R, int64_t n
     if (!M) return 0;
     const size_t rb = precision == FTH_FP64 ? 8 : 4;
     const size_t n = size_t(M->n);
+    // (p, s) rows are padded to whole groups of 128 / (R rb) rows (when R rb < 128)
+    const size_t grp = R > 0 && size_t(R) * rb < 128 ? 128 / (size_t(R) * rb) : 1;
+    const size_t ps_rows = (n + grp - 1) / grp * grp;
     size_t bytes = 0;
     if (M->format == FTH_CSR) {
         bytes += (n + 1) * 8 + size_t(M->nnz) * (4 + rb);
-        bytes += n * size_t(R) * rb * size_t(3 + ns);
+        bytes += n * size_t(R) * rb * 2 + ps_rows * size_t(R) * rb * size_t(1 + ns);
     } else {
         const size_t P = (n + 255) / 256 * 256;
         const size_t ks = P >= 2048 ? 8 : P / 256;
         bytes += P * P * (precision == FTH_FP32_BF16X3 ? 4 : rb);           // M (hi + lo, or FP64)
-        bytes += 2 * P * size_t(R) * rb + n * size_t(R) * rb * size_t(1 + ns);  // q pair (padded), p and s
+        bytes += 2 * P * size_t(R) * rb + ps_rows * size_t(R) * rb * size_t(1 + ns);  // q pair (padded), p and s
         bytes += ks * P * size_t(R) * rb;                                      // split-K partials
         if (precision == FTH_FP32_BF16X3) bytes += P * size_t(R) * 4;          // bf16 q split
     }
@@ -952,23 +959,25 @@ fth_status fth_get_state(fth_ctx* c, double* q, double* p, double* s) {
     HIP_OK(hipStreamSynchronize(c->stream));
     const size_t cnt = size_t(c->n) * size_t(c->R);
     const size_t D = size_t(c->ns + 1), R = size_t(c->R);
-    std::vector<double> qh(cnt), psh(cnt * D);
+    const size_t pscnt = c->ps_bytes() / c->real_bytes();
+    std::vector<double> qh(cnt), psh(pscnt);
     if (c->prec == FTH_FP64) {
         HIP_OK(hipMemcpy(qh.data(), c->d_q[c->step & 1], sizeof(double) * cnt, hipMemcpyDeviceToHost));
-        HIP_OK(hipMemcpy(psh.data(), c->d_ps, sizeof(double) * cnt * D, hipMemcpyDeviceToHost));
+        HIP_OK(hipMemcpy(psh.data(), c->d_ps, sizeof(double) * pscnt, hipMemcpyDeviceToHost));
     } else {
-        std::vector<float> tq(cnt), tps(cnt * D);
+        std::vector<float> tq(cnt), tps(pscnt);
         HIP_OK(hipMemcpy(tq.data(), c->d_q[c->step & 1], sizeof(float) * cnt, hipMemcpyDeviceToHost));
-        HIP_OK(hipMemcpy(tps.data(), c->d_ps, sizeof(float) * cnt * D, hipMemcpyDeviceToHost));
+        HIP_OK(hipMemcpy(tps.data(), c->d_ps, sizeof(float) * pscnt, hipMemcpyDeviceToHost));
         for (size_t k = 0; k < cnt; ++k) qh[k] = tq[k];
-        for (size_t k = 0; k < cnt * D; ++k) psh[k] = tps[k];
+        for (size_t k = 0; k < pscnt; ++k) psh[k] = tps[k];
     }
     if (q) std::memcpy(q, qh.data(), sizeof(double) * cnt);
     for (size_t i = 0; i < size_t(c->n); ++i)
         for (size_t r = 0; r < R; ++r) {
-            if (p) p[i * R + r] = psh[(i * D) * R + r];
+            if (p) p[i * R + r] = psh[c->ps_offset(int64_t(i), 0, int(r))];
             if (s)
-                for (size_t k = 0; k + 1 < D; ++k) s[(k * size_t(c->n) + i) * R + r] = psh[(i * D + k + 1) * R + r];
+                for (size_t k = 0; k + 1 < D; ++k)
+                    s[(k * size_t(c->n) + i) * R + r] = psh[c->ps_offset(int64_t(i), int(k + 1), int(r))];
         }
     return FTH_OK;
 }
@@ -993,19 +1002,21 @@ fth_status fth_set_state(fth_ctx* c, const double* q, const double* p, const dou
     }
     if (p || s) {
         // read-modify-write of the interleaved (p, s) block
-        std::vector<double> psh(cnt * D);
+        const size_t pscnt = c->ps_bytes() / rb;
+        std::vector<double> psh(pscnt);
         if (f64) {
-            HIP_OK(hipMemcpy(psh.data(), c->d_ps, sizeof(double) * cnt * D, hipMemcpyDeviceToHost));
+            HIP_OK(hipMemcpy(psh.data(), c->d_ps, sizeof(double) * pscnt, hipMemcpyDeviceToHost));
         } else {
-            std::vector<float> t(cnt * D);
-            HIP_OK(hipMemcpy(t.data(), c->d_ps, rb * cnt * D, hipMemcpyDeviceToHost));
-            for (size_t k = 0; k < cnt * D; ++k) psh[k] = t[k];
+            std::vector<float> t(pscnt);
+            HIP_OK(hipMemcpy(t.data(), c->d_ps, rb * pscnt, hipMemcpyDeviceToHost));
+            for (size_t k = 0; k < pscnt; ++k) psh[k] = t[k];
         }
         for (size_t i = 0; i < size_t(c->n); ++i)
             for (size_t r = 0; r < R; ++r) {
-                if (p) psh[(i * D) * R + r] = p[i * R + r];
+                if (p) psh[c->ps_offset(int64_t(i), 0, int(r))] = p[i * R + r];
                 if (s)
-                    for (size_t k = 0; k + 1 < D; ++k) psh[(i * D + k + 1) * R + r] = s[(k * size_t(c->n) + i) * R + r];
+                    for (size_t k = 0; k + 1 < D; ++k)
+                        psh[c->ps_offset(int64_t(i), int(k + 1), int(r))] = s[(k * size_t(c->n) + i) * R + r];
             }
         HIP_OK(put(c->d_ps, psh));
     }

@@ -45,7 +45,9 @@ struct fth_ctx {
     std::vector<double> m_host;  // dense M kept until R fixes the path (n <= 4096)
     bool m_uploaded = false;
     void* d_q[2] = {nullptr, nullptr};
-    void* d_ps = nullptr;  // [n][ns+1][R]: p then s_1..s_ns per row
+    void* d_ps = nullptr;  // p then s_1..s_ns, rows grouped by 2^ps_lg (see ps_offset)
+    int ps_lg = 0;         // log2 of rows per (p, s) group
+    int64_t ps_rows = 0;   // n rounded up to whole groups
     double* d_acc = nullptr;  // [3][n_out]: blk, s1, s2 (pairs first, then diagonal)
     int64_t* d_step = nullptr;
     int32_t* d_flag = nullptr;
@@ -89,6 +91,13 @@ struct fth_ctx {
     bool mfma() const { return dense() && !small; }
     int64_t q_rows() const { return mfma() ? rows_pad : n; }
     int64_t n_out() const { return npairs + (opt.acc_diag ? n : 0); }
+    size_t ps_bytes() const { return size_t(ps_rows) * size_t(R) * size_t(ns + 1) * real_bytes(); }
+    // element offset of (row i, component c, replica r) in the (p, s) buffer:
+    // groups of 2^ps_lg rows, each component of a group a contiguous [2^ps_lg][R] block
+    size_t ps_offset(int64_t i, int c, int r) const {
+        const int64_t g = i >> ps_lg, w = i & ((int64_t(1) << ps_lg) - 1);
+        return size_t((((g * (ns + 1) + c) << ps_lg) + w) * R + r);
+    }
 
     void dfree(void*& p) {
         for (auto it = allocs.begin(); it != allocs.end(); ++it)

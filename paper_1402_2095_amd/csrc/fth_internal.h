@@ -27,10 +27,12 @@ struct StepArgs {
     // small dense systems: M [N][N] row-major in state precision; kept in LDS if m_in_lds
     const Real* mdense;
     int32_t m_in_lds;
-    // state: q ping-pong [rows][R]; p and s interleaved per row, ps[rows][ns+1][R]
+    // state: q ping-pong [rows][R]; p and s in groups of 2^ps_lg rows, component-major
+    // inside a group: ps[row >> ps_lg][ns+1][row & (2^ps_lg - 1)][R] (p is component 0)
     Real* q0;
     Real* q1;
     Real* ps;
+    int32_t ps_lg;
     // propagator T then S, each (ns+1)^2 row-major, state precision
     const Real* TS;
     Real h;

@@ -115,6 +115,16 @@ __device__ __forceinline__ void pair_update(const StepArgs<Real>& a, const StepI
     if (si.rq == 0 && si.acc_on) acc_update(a.pblk, a.ps1, a.ps2, pk, x, si.close);
 }
 
+// (p, s) of row i: rows are grouped by 2^lg, and inside a group each component
+// is a contiguous [2^lg][R] block, so one component of a group spans at least
+// a 128-byte line whatever R is.  Returns the row's component-0 slice;
+// component c is at + c * ps_stride(R, lg).
+template <typename Real>
+__device__ __forceinline__ Real* ps_row(Real* ps, int64_t i, int D, int64_t R, int lg) {
+    return ps + ((((i >> lg) * D) << lg) + (i & ((int64_t(1) << lg) - 1))) * R;
+}
+__device__ __forceinline__ int64_t ps_stride(int64_t R, int lg) { return R << lg; }
+
 // The thread's slice of one row's state.
 template <typename Real, int NS, int RPT>
 struct RowState {
@@ -129,10 +139,11 @@ __device__ __forceinline__ RowState<Real, NS, RPT> load_row(const StepArgs<Real>
     const int64_t R = a.R;
     constexpr int D = NS + 1;
     st.q = load_vec<Real, RPT>(qr + i * R + r0);
-    const Real* psrow = a.ps + i * (D * R) + r0;
+    const Real* psrow = ps_row(a.ps, i, D, R, a.ps_lg) + r0;
+    const int64_t cs = ps_stride(R, a.ps_lg);
     st.p = load_state<Real, RPT, NT>(psrow);
 #pragma unroll
-    for (int c = 0; c < NS; ++c) st.s[c] = load_state<Real, RPT, NT>(psrow + (c + 1) * R);
+    for (int c = 0; c < NS; ++c) st.s[c] = load_state<Real, RPT, NT>(psrow + (c + 1) * cs);
     return st;
 }
 
@@ -197,10 +208,11 @@ __device__ __forceinline__ Vec<Real, RPT> finish_row(const StepArgs<Real>& a, co
     }
     RowState<Real, NS, RPT> nx;
     const bool ok = ou_update<Real, NS, RPT>(a.TS, a.TS + D * D, a.h, a.hh, st, acc, xi, nx);
-    Real* psrow = a.ps + i * (D * R) + si.r0;
+    Real* psrow = ps_row(a.ps, i, D, R, a.ps_lg) + si.r0;
+    const int64_t cs = ps_stride(R, a.ps_lg);
     store_state<Real, RPT, NT>(psrow, nx.p);
 #pragma unroll
-    for (int c = 0; c < NS; ++c) store_state<Real, RPT, NT>(psrow + (c + 1) * R, nx.s[c]);
+    for (int c = 0; c < NS; ++c) store_state<Real, RPT, NT>(psrow + (c + 1) * cs, nx.s[c]);
     store_state<Real, RPT, NT>(qw + i * R + si.r0, nx.q);
     if (!ok) atomicOr(a.flag, 1);
     return nx.q;

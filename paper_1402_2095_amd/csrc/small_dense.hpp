@@ -50,10 +50,11 @@ __global__ __launch_bounds__(1024) void small_dense_kernel(const StepArgs<Real> 
     RowState<Real, NS, RPT> st;
     if (active) {
         st.q = load_vec<Real, RPT>(qg + i * R + r0);
-        const Real* psrow = a.ps + i * (D * R) + r0;
+        const Real* psrow = ps_row(a.ps, i, D, R, a.ps_lg) + r0;
+        const int64_t cs = ps_stride(R, a.ps_lg);
         st.p = load_vec<Real, RPT>(psrow);
 #pragma unroll
-        for (int c = 0; c < NS; ++c) st.s[c] = load_vec<Real, RPT>(psrow + (c + 1) * R);
+        for (int c = 0; c < NS; ++c) st.s[c] = load_vec<Real, RPT>(psrow + (c + 1) * cs);
     }
     const Real* T = a.TS;
     const Real* S = a.TS + D * D;
@@ -123,10 +124,11 @@ __global__ __launch_bounds__(1024) void small_dense_kernel(const StepArgs<Real> 
     Real* qgo = (nend & 1) ? a.q1 : a.q0;
     if (active) {
         store_vec<Real, RPT>(qgo + i * R + r0, st.q);
-        Real* psrow = a.ps + i * (D * R) + r0;
+        Real* psrow = ps_row(a.ps, i, D, R, a.ps_lg) + r0;
+        const int64_t cs = ps_stride(R, a.ps_lg);
         store_vec<Real, RPT>(psrow, st.p);
 #pragma unroll
-        for (int c = 0; c < NS; ++c) store_vec<Real, RPT>(psrow + (c + 1) * R, st.s[c]);
+        for (int c = 0; c < NS; ++c) store_vec<Real, RPT>(psrow + (c + 1) * cs, st.s[c]);
     }
     for (int64_t x = tid; x < a.npairs; x += nthr) a.pblk[x] = bl[x];
     for (int64_t x = tid; x < nd; x += nthr) a.dblk[x] = bl[a.npairs + x];

@@ -59,10 +59,11 @@ __global__ __launch_bounds__(tb_max_block(sizeof(Real) == 8, NS)) void tb_step_k
     int32_t pslot = -1;
     if (row_ok) {
         st.q = load_vec<Real, RPT>(qg + i * R + r0);
-        const Real* psrow = tb.ps_in + i * (D * R) + r0;
+        const Real* psrow = ps_row(tb.ps_in, i, D, R, a.ps_lg) + r0;
+        const int64_t cs = ps_stride(R, a.ps_lg);
         st.p = load_vec<Real, RPT>(psrow);
 #pragma unroll
-        for (int c = 0; c < NS; ++c) st.s[c] = load_vec<Real, RPT>(psrow + (c + 1) * R);
+        for (int c = 0; c < NS; ++c) st.s[c] = load_vec<Real, RPT>(psrow + (c + 1) * cs);
         const int64_t kb = a.row_ptr[i], ke = a.row_ptr[i + 1];
         nz = int(ke - kb);
 #pragma unroll
@@ -129,10 +130,11 @@ __global__ __launch_bounds__(tb_max_block(sizeof(Real) == 8, NS)) void tb_step_k
     }
     if (output) {
         store_state<Real, RPT, true>(qgo + i * R + r0, st.q);
-        Real* psrow = tb.ps_out + i * (D * R) + r0;
+        Real* psrow = ps_row(tb.ps_out, i, D, R, a.ps_lg) + r0;
+        const int64_t cs = ps_stride(R, a.ps_lg);
         store_state<Real, RPT, true>(psrow, st.p);
 #pragma unroll
-        for (int c = 0; c < NS; ++c) store_state<Real, RPT, true>(psrow + (c + 1) * R, st.s[c]);
+        for (int c = 0; c < NS; ++c) store_state<Real, RPT, true>(psrow + (c + 1) * cs, st.s[c]);
         if (a.dblk != nullptr && rq == 0) a.dblk[i] = blk;
         if (!ok) atomicOr(a.flag, 1);
     }
