@@ -97,17 +97,28 @@ def dense_roofline(M, ns: int, R: int, npairs: int, prec: int, per_step_s: float
     return float(mbytes + state + part), flops
 
 
-def algorithmic_bytes(M, ns: int, R: int, npairs: int, prec: int, steps_per_launch: int = 1) -> float:
+def coded_matrix_bytes(M, b: int) -> float:
+    """Bytes of the coded sparse form: 8 one-byte column codes per row, and 8
+    one-byte value codes (values in a table when there are at most 256
+    distinct ones at state precision) or 8 raw values per row."""
+    vals = M.val.astype(np.float64 if b == 8 else np.float32)
+    table = np.unique(vals).size <= 256
+    return float(M.n * (8 + (8 if table else 8 * b)))
+
+
+def algorithmic_bytes(M, ns: int, R: int, npairs: int, prec: int, steps_per_launch: int = 1,
+                      coded: bool = False) -> float:
     """Bytes one launch must move at minimum: state q (read q_n, write
-    q_{n+k}), p and s_1..s_ns read and written; the CSR arrays once (row_ptr
-    8 B, col 4 B, value per nonzero); the diagonal block accumulator read and
-    written (FP64); per step, each pair's two q rows and its accumulator.  A
-    blocked launch advancing k steps moves the state and the matrix once."""
+    q_{n+k}), p and s_1..s_ns read and written; the matrix once (CSR: row_ptr
+    8 B, col 4 B and a value per nonzero; or the coded form); the diagonal
+    block accumulator read and written (FP64); per step, each pair's two q
+    rows and its accumulator.  A blocked launch advancing k steps moves the
+    state and the matrix once."""
     from paper_1402_2095_amd import fth
     b = 8 if prec == fth.FTH_FP64 else 4
     n = M.n
     state = 2 * (ns + 2) * b * n * R
-    csr = (n + 1) * 8 + M.nnz * (4 + b)
+    csr = coded_matrix_bytes(M, b) if coded else (n + 1) * 8 + M.nnz * (4 + b)
     diag = 16 * n
     pairs = steps_per_launch * npairs * (2 * R * b + 16 + 8)
     return float(state + csr + diag + pairs)
@@ -145,10 +156,11 @@ def unit_of(kernel_name: str):
     if m:
         real, ns, kt = m.group(1), m.group(2), int(m.group(3))
         return "tb", [f"tb_step_kernel<{real}, {ns}, 4, {kt}>", f"tb_pairs_kernel<{real}, 4, {kt}>"], kt
-    m = re.search(r"csr_step_kernel<(\w+),NS=(\d+),RPT=(\d+),NT=(\d)>", kernel_name)
+    m = re.search(r"csr_step_kernel<(\w+),NS=(\d+),RPT=(\d+),NT=(\d),CODED=(\d)>", kernel_name)
     if m:
-        real, ns, rpt, nt = m.groups()
-        return "csr", [f"csr_step_kernel<{real}, {ns}, {rpt}, {'true' if nt == '1' else 'false'}>"], 1
+        real, ns, rpt, nt, coded = m.groups()
+        tf = {"0": "false", "1": "true"}
+        return "csr", [f"csr_step_kernel<{real}, {ns}, {rpt}, {tf[nt]}, {tf[coded]}>"], 1
     m = re.search(r"(gemm_bf16x3_kernel|gemm_f64_kernel)<RT=(\d+),ksplit=\d+> \+ "
                   r"dense_epilogue_kernel<(\w+),NS=(\d+),RPT=(\d+),NT=(\d)>", kernel_name)
     if m:
@@ -461,7 +473,7 @@ def main():
     elif kind == "tb":
         abytes = algorithmic_bytes(M, g.ns, R, len(pairs), prec, steps_per_launch=unit_steps)
     else:
-        abytes = algorithmic_bytes(M, g.ns, R, len(pairs), prec)
+        abytes = algorithmic_bytes(M, g.ns, R, len(pairs), prec, coded="CODED=1" in sol.kernel_name)
     achieved = abytes / per_unit_s / 1e9
     hbm = {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
            "frac": achieved / HBM_PEAK_GBS, "traffic": traffic}

@@ -127,6 +127,11 @@ typedef struct {
                                 matrix makes fth_run fail with FTH_EUNSUPPORTED. */
     int32_t temporal_threads; /* threads per blocked workgroup: 256, 512 or 1024 (0: the largest
                                  allowed for the GLE size and precision) */
+    int32_t coded_matrix;    /* CSR with <= 8 entries per row and <= 255 distinct column offsets
+                                j - i: 0 also keeps a coded copy (one-byte codes into tables of
+                                the distinct offsets and, if <= 256, distinct values) that the
+                                one-step kernel reads for R >= 4; -1: plain CSR only.  Results
+                                are identical either way. */
 } fth_options;
 
 /* Fill *opt with defaults: seed 0, stream 0, FTH_FP32, burn_in 0,

@@ -81,13 +81,77 @@ __device__ __forceinline__ void csr_row(const StepArgs<Real>& a, const StepInfo&
     (void)finish_row<Real, NS, RPT, NT>(a, si, i, st, acc, xi, qw);
 }
 
+// One row in the coded form: the row's 8 column codes and 8 value codes are
+// two 8-byte loads; codes index the offset and value tables staged in LDS.
+// Slots keep the CSR order, so the sum is the plain form's, bit for bit.
 template <typename Real, int NS, int RPT, bool NT>
+__device__ __forceinline__ void coded_row(const StepArgs<Real>& a, const StepInfo& si, int64_t i, const Real* qr,
+                                          Real* qw, const int32_t* s_off, const Real* s_val) {
+    using V = Vec<Real, RPT>;
+    const int64_t R = a.R;
+    constexpr int G = 4;  // slots gathered per batch (two batches)
+    const uint64_t cc = a.ell_col[i];
+    const uint64_t vc = a.ell_vcode != nullptr ? a.ell_vcode[i] : 0;
+    const RowState<Real, NS, RPT> st = load_row<Real, NS, RPT, NT>(a, qr, i, si.r0);
+    auto value = [&](int u) -> Real {
+        return a.ell_vcode != nullptr ? s_val[(vc >> (8 * u)) & 255u] : a.ell_vraw[i * kCodedSlots + u];
+    };
+    V qj[G];
+    Real vj[G];
+#pragma unroll
+    for (int u = 0; u < G; ++u) {
+        const uint32_t code = uint32_t(cc >> (8 * u)) & 255u;
+        vj[u] = Real(0);
+        if (code != 255u) {
+            vj[u] = value(u);
+            qj[u] = load_vec<Real, RPT>(qr + (i + s_off[code]) * R + si.r0);
+        }
+    }
+    Real xi[NS + 1][RPT];
+    row_noise<Real, NS, RPT>(a, si, i, xi);
+    Real acc[RPT];
+#pragma unroll
+    for (int m = 0; m < RPT; ++m) acc[m] = Real(0);
+#pragma unroll
+    for (int u = 0; u < G; ++u)
+        if (((cc >> (8 * u)) & 255u) != 255u) {
+#pragma unroll
+            for (int m = 0; m < RPT; ++m) acc[m] = fmaR(vj[u], qj[u].v[m], acc[m]);
+        }
+    if ((cc >> (8 * G)) != ~uint64_t(0) >> (8 * G)) {  // second batch not empty
+#pragma unroll
+        for (int u = 0; u < G; ++u) {
+            const uint32_t code = uint32_t(cc >> (8 * (G + u))) & 255u;
+            vj[u] = Real(0);
+            if (code != 255u) {
+                vj[u] = value(G + u);
+                qj[u] = load_vec<Real, RPT>(qr + (i + s_off[code]) * R + si.r0);
+            }
+        }
+#pragma unroll
+        for (int u = 0; u < G; ++u)
+            if (((cc >> (8 * (G + u))) & 255u) != 255u) {
+#pragma unroll
+                for (int m = 0; m < RPT; ++m) acc[m] = fmaR(vj[u], qj[u].v[m], acc[m]);
+            }
+    }
+    (void)finish_row<Real, NS, RPT, NT>(a, si, i, st, acc, xi, qw);
+}
+
+template <typename Real, int NS, int RPT, bool NT, bool CODED>
 __global__ __launch_bounds__(256) void csr_step_kernel(const StepArgs<Real> a, const int k) {
     const StepInfo si = step_info<Real, RPT>(a, k);
     const Real* __restrict__ qr = (si.n & 1) ? a.q1 : a.q0;
     Real* __restrict__ qw = (si.n & 1) ? a.q0 : a.q1;
     const int per_block = blockDim.x >> a.lg_tpr;
     const int64_t b = blockIdx.x;
+    __shared__ int32_t s_off[CODED ? kCodedMaxOffsets : 1];
+    __shared__ Real s_val[CODED ? kCodedMaxValues : 1];
+    if constexpr (CODED) {  // every thread reaches the barrier
+        for (int t = int(threadIdx.x); t < a.n_off; t += int(blockDim.x)) s_off[t] = a.dict_off[t];
+        for (int t = int(threadIdx.x); t < a.n_val; t += int(blockDim.x)) s_val[t] = a.dict_val[t];
+        __syncthreads();
+    }
 
     if (b >= a.row_tiles_padded) {
         const int64_t pk = (b - a.row_tiles_padded) * per_block + si.slot;
@@ -99,7 +163,10 @@ __global__ __launch_bounds__(256) void csr_step_kernel(const StepArgs<Real> a, c
     if (t >= a.row_tiles) return;
     const int64_t i = t * per_block + si.slot;
     if (i >= a.N) return;
-    csr_row<Real, NS, RPT, NT>(a, si, i, qr, qw);
+    if constexpr (CODED)
+        coded_row<Real, NS, RPT, NT>(a, si, i, qr, qw, s_off, s_val);
+    else
+        csr_row<Real, NS, RPT, NT>(a, si, i, qr, qw);
 }
 
 // ---------------------------------------------------------------- dispatch
@@ -141,7 +208,18 @@ const void* pick_kernel(const StepLaunch& L) {
 
 template <typename Real, int NS, int RPT, bool NT>
 struct CsrKernel {
-    static const void* fn() { return reinterpret_cast<const void*>(&csr_step_kernel<Real, NS, RPT, NT>); }
+    static const void* fn() { return reinterpret_cast<const void*>(&csr_step_kernel<Real, NS, RPT, NT, false>); }
+};
+
+// The coded form is instantiated for 4 and 8 replicas per thread only.
+template <typename Real, int NS, int RPT, bool NT>
+struct CodedKernel {
+    static const void* fn() {
+        if constexpr (RPT >= 4)
+            return reinterpret_cast<const void*>(&csr_step_kernel<Real, NS, RPT, NT, true>);
+        else
+            return nullptr;
+    }
 };
 
 template <typename Real>
@@ -160,7 +238,8 @@ int launch_step_kernel(const void* fn, const StepArgs<Real>& a, const StepLaunch
 
 template <typename Real>
 int launch_csr_step_impl(const StepArgs<Real>& a, const StepLaunch& L, int k, void* stream) {
-    return dev::launch_step_kernel<Real>(dev::pick_kernel<dev::CsrKernel, Real>(L), a, L, k, stream);
+    const void* fn = L.coded ? dev::pick_kernel<dev::CodedKernel, Real>(L) : dev::pick_kernel<dev::CsrKernel, Real>(L);
+    return dev::launch_step_kernel<Real>(fn, a, L, k, stream);
 }
 
 }  // namespace fth

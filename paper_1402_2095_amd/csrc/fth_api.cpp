@@ -12,6 +12,7 @@
 #include <map>
 #include <string>
 #include <tuple>
+#include <type_traits>
 #include <vector>
 
 #include "fth_ctx.hpp"
@@ -179,6 +180,85 @@ fth_status upload_converted(fth_ctx* c, void** dst, const void* src, int64_t cou
     return FTH_OK;
 }
 
+// Coded copy of a CSR matrix with at most 8 entries per row: one-byte codes
+// into the tables of distinct column offsets j - i and distinct values (at
+// state precision), slots in CSR order.  Left out (plain CSR only) when there
+// are more than 255 distinct offsets; values stay raw when there are more
+// than 256 distinct ones.
+template <typename Real>
+fth_status build_coded(fth_ctx* c, const fth_matrix* M) {
+    const int64_t n = M->n;
+    std::map<int64_t, int32_t> offs;
+    for (int64_t i = 0; i < n; ++i)
+        for (int64_t k = M->row_ptr[i]; k < M->row_ptr[i + 1]; ++k) {
+            offs.emplace(int64_t(M->col[k]) - i, 0);
+            if (int(offs.size()) > fth::kCodedMaxOffsets) return FTH_OK;
+        }
+    std::vector<int32_t> off_tab;
+    for (auto& kv : offs) {
+        kv.second = int32_t(off_tab.size());
+        off_tab.push_back(int32_t(kv.first));
+    }
+    auto value = [&](int64_t k) -> Real {
+        return M->value_is_f64 ? Real(static_cast<const double*>(M->val)[k]) : Real(static_cast<const float*>(M->val)[k]);
+    };
+    // distinct values by bit pattern (so -0 and +0 stay distinct, NaN cannot occur: M is validated)
+    using Bits = typename std::conditional<sizeof(Real) == 8, uint64_t, uint32_t>::type;
+    std::map<Bits, int32_t> vals;
+    bool vtab = true;
+    for (int64_t k = 0; k < M->nnz && vtab; ++k) {
+        const Real v = value(k);
+        Bits b;
+        std::memcpy(&b, &v, sizeof(b));
+        vals.emplace(b, 0);
+        vtab = int(vals.size()) <= fth::kCodedMaxValues;
+    }
+    std::vector<Real> val_tab;
+    if (vtab)
+        for (auto& kv : vals) {
+            kv.second = int32_t(val_tab.size());
+            Real v;
+            std::memcpy(&v, &kv.first, sizeof(v));
+            val_tab.push_back(v);
+        }
+    std::vector<uint64_t> cc(static_cast<size_t>(n)), vc(vtab ? static_cast<size_t>(n) : 0);
+    std::vector<Real> vraw(vtab ? 0 : size_t(n) * fth::kCodedSlots, Real(0));
+    for (int64_t i = 0; i < n; ++i) {
+        uint64_t ccode = ~uint64_t(0), vcode = 0;
+        for (int64_t k = M->row_ptr[i], u = 0; k < M->row_ptr[i + 1]; ++k, ++u) {
+            const uint64_t oc = uint64_t(offs[int64_t(M->col[k]) - i]);
+            ccode = (ccode & ~(uint64_t(255) << (8 * u))) | (oc << (8 * u));
+            const Real v = value(k);
+            if (vtab) {
+                Bits b;
+                std::memcpy(&b, &v, sizeof(b));
+                vcode |= uint64_t(vals[b]) << (8 * u);
+            } else {
+                vraw[size_t(i) * fth::kCodedSlots + size_t(u)] = v;
+            }
+        }
+        cc[size_t(i)] = ccode;
+        if (vtab) vc[size_t(i)] = vcode;
+    }
+    HIP_OK(c->dalloc(reinterpret_cast<void**>(&c->d_ell_col), sizeof(uint64_t) * cc.size()));
+    HIP_OK(hipMemcpy(c->d_ell_col, cc.data(), sizeof(uint64_t) * cc.size(), hipMemcpyHostToDevice));
+    HIP_OK(c->dalloc(reinterpret_cast<void**>(&c->d_dict_off), sizeof(int32_t) * off_tab.size()));
+    HIP_OK(hipMemcpy(c->d_dict_off, off_tab.data(), sizeof(int32_t) * off_tab.size(), hipMemcpyHostToDevice));
+    c->n_off = int32_t(off_tab.size());
+    if (vtab) {
+        HIP_OK(c->dalloc(reinterpret_cast<void**>(&c->d_ell_vcode), sizeof(uint64_t) * vc.size()));
+        HIP_OK(hipMemcpy(c->d_ell_vcode, vc.data(), sizeof(uint64_t) * vc.size(), hipMemcpyHostToDevice));
+        HIP_OK(c->dalloc(&c->d_dict_val, sizeof(Real) * val_tab.size()));
+        HIP_OK(hipMemcpy(c->d_dict_val, val_tab.data(), sizeof(Real) * val_tab.size(), hipMemcpyHostToDevice));
+        c->n_val = int32_t(val_tab.size());
+    } else {
+        HIP_OK(c->dalloc(&c->d_ell_vraw, sizeof(Real) * vraw.size()));
+        HIP_OK(hipMemcpy(c->d_ell_vraw, vraw.data(), sizeof(Real) * vraw.size(), hipMemcpyHostToDevice));
+    }
+    c->coded = true;
+    return FTH_OK;
+}
+
 template <typename Real>
 fth_status upload_TS(fth_ctx* c) {
     const int d = c->ns + 1;
@@ -325,6 +405,13 @@ fth::StepArgs<Real> step_args(fth_ctx* c) {
     fth::StepArgs<Real> a{};
     a.row_ptr = c->d_row_ptr;
     a.col = c->d_col;
+    a.ell_col = c->d_ell_col;
+    a.ell_vcode = c->d_ell_vcode;
+    a.ell_vraw = static_cast<const Real*>(c->d_ell_vraw);
+    a.dict_off = c->d_dict_off;
+    a.dict_val = static_cast<const Real*>(c->d_dict_val);
+    a.n_off = c->n_off;
+    a.n_val = c->n_val;
     a.val = static_cast<const Real*>(c->d_val);
     a.part = static_cast<const Real*>(c->d_part);
     a.ksplit = c->ksplit;
@@ -371,7 +458,8 @@ fth::StepArgs<Real> step_args(fth_ctx* c) {
 
 fth::StepLaunch step_launch(fth_ctx* c) {
     const int per_block = c->block / (c->R / c->rpt);
-    return fth::StepLaunch{c->ns, c->rpt, c->nt, c->block, (c->npairs + per_block - 1) / per_block};
+    return fth::StepLaunch{c->ns, c->rpt, c->nt, c->coded && c->rpt >= 4, c->block,
+                           (c->npairs + per_block - 1) / per_block};
 }
 
 fth::DenseGemmArgs gemm_args(fth_ctx* c, int k) {
@@ -786,6 +874,7 @@ fth_status fth_create(const fth_matrix* M, const fth_gle* gle, double dt, const 
     if (opt.temporal_threads != 0 && opt.temporal_threads != 256 && opt.temporal_threads != 512 &&
         opt.temporal_threads != 1024)
         return fail(FTH_EINVAL, "temporal_threads must be 0, 256, 512 or 1024");
+    if (opt.coded_matrix != 0 && opt.coded_matrix != -1) return fail(FTH_EINVAL, "coded_matrix must be 0 or -1");
     if (npairs < 0 || (npairs > 0 && !pairs)) return fail(FTH_EINVAL, "invalid pair list");
     for (int64_t k = 0; k < 2 * npairs; ++k)
         if (pairs[k] < 0 || pairs[k] >= M->n) return fail(FTH_EINVAL, "pair index out of range at %lld", (long long)k);
@@ -842,6 +931,10 @@ fth_status fth_create(const fth_matrix* M, const fth_gle* gle, double dt, const 
         st = c->prec == FTH_FP64 ? upload_converted<double>(c.get(), &c->d_val, M->val, M->nnz, M->value_is_f64)
                                  : upload_converted<float>(c.get(), &c->d_val, M->val, M->nnz, M->value_is_f64);
         if (st != FTH_OK) return st;
+        if (opt.coded_matrix == 0 && c->max_row_nnz <= fth::kCodedSlots) {
+            st = c->prec == FTH_FP64 ? build_coded<double>(c.get(), M) : build_coded<float>(c.get(), M);
+            if (st != FTH_OK) return st;
+        }
     }
     st = c->prec == FTH_FP64 ? upload_TS<double>(c.get()) : upload_TS<float>(c.get());
     if (st != FTH_OK) return st;
@@ -1107,9 +1200,9 @@ fth_status fth_kernel_name(const fth_ctx* c, char* name, size_t len) {
                       c->prec == FTH_FP64 ? "double" : "float", c->ns, c->tb_kt, c->tb_block, c->block,
                       c->tuned ? " (autotuned)" : "");
     else
-        std::snprintf(name, len, "csr_step_kernel<%s,NS=%d,RPT=%d,NT=%d> block=%d%s",
-                      c->prec == FTH_FP64 ? "double" : "float", c->ns, c->rpt, int(c->nt), c->block,
-                      c->tuned ? " (autotuned)" : "");
+        std::snprintf(name, len, "csr_step_kernel<%s,NS=%d,RPT=%d,NT=%d,CODED=%d> block=%d%s",
+                      c->prec == FTH_FP64 ? "double" : "float", c->ns, c->rpt, int(c->nt),
+                      int(c->coded && c->rpt >= 4), c->block, c->tuned ? " (autotuned)" : "");
     return FTH_OK;
 }
 

@@ -51,6 +51,14 @@ struct fth_ctx {
     double* d_acc = nullptr;  // [3][n_out]: blk, s1, s2 (pairs first, then diagonal)
     int64_t* d_step = nullptr;
     int32_t* d_flag = nullptr;
+    // coded sparse form: per row 8 one-byte column / value codes into tables
+    bool coded = false;
+    uint64_t* d_ell_col = nullptr;    // [n]
+    uint64_t* d_ell_vcode = nullptr;  // [n] or null
+    void* d_ell_vraw = nullptr;       // [n][8] when the values do not fit a table
+    int32_t* d_dict_off = nullptr;
+    void* d_dict_val = nullptr;
+    int32_t n_off = 0, n_val = 0;
     // temporal blocking of narrow-band CSR systems
     int64_t band_w = -1;   // half-bandwidth max |j - i| of the CSR pattern
     int max_row_nnz = 0;   // longest CSR row

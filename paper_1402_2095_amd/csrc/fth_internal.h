@@ -18,6 +18,16 @@ struct StepArgs {
     const int64_t* row_ptr;
     const int32_t* col;
     const Real* val;
+    // force source, sparse, coded form (rows of at most 8 entries, CSR order): per row
+    // 8 one-byte column codes (255: empty slot) into the table of distinct offsets
+    // j - i, and 8 one-byte value codes into the table of distinct values, or, when
+    // the values do not fit a table, 8 raw values per row
+    const uint64_t* ell_col;   // [N], null: plain CSR
+    const uint64_t* ell_vcode; // [N], null: raw values in ell_vraw
+    const Real* ell_vraw;      // [N][8]
+    const int32_t* dict_off;   // [n_off]
+    const Real* dict_val;      // [n_val]
+    int32_t n_off, n_val;
     // force source, dense: split-K partial sums [ksplit][rows_pad][R] of M q_n
     const Real* part;
     int32_t ksplit;
@@ -62,10 +72,15 @@ struct StepArgs {
 };
 
 // Launch shape of a step kernel.
+constexpr int kCodedSlots = 8;       // entries per row of the coded sparse form
+constexpr int kCodedMaxOffsets = 255;  // distinct column offsets (code 255 marks an empty slot)
+constexpr int kCodedMaxValues = 256;   // distinct values held in a table
+
 struct StepLaunch {
     int ns;              // extra GLE momenta (template)
     int rpt;             // replicas per thread (template: 1, 2, 4, 8)
     bool nt;             // streaming (non-temporal) state loads/stores (template)
+    bool coded;          // coded sparse form (template; replicas per thread 4 or 8)
     int block;           // threads per workgroup
     int64_t pair_tiles;  // extra workgroups for the selected pairs
 };

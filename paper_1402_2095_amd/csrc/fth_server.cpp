@@ -320,6 +320,7 @@ fth_status fth_server_submit(fth_server* s, const fth_request* q, uint64_t* id) 
     r->opt.block_len = q->block_len > 0 ? q->block_len : 100;
     r->opt.replicas = q->replicas > 0 ? q->replicas : (M.format == FTH_CSR ? 32 : 64);
     r->opt.steps_per_graph = s->opt.steps_per_tick;
+    r->opt.coded_matrix = -1;  // the packed kernel reads plain CSR; keep the footprint as admitted
     r->target = q->target_rel_stderr;
     r->max_steps = q->max_steps;
     // normalisation of off-diagonal estimates by the request's own diagonals

@@ -276,3 +276,64 @@ def test_autotuner_keeps_trajectory():
     for x, y in zip(a.accumulators()[:3], b.accumulators()[:3]):
         assert np.allclose(x, y, rtol=1e-12, atol=0)
     assert a.accumulators()[4] == b.accumulators()[4] == 60
+
+
+def random_symmetric_csr(n, per_row, seed):
+    """Symmetric sparse SPD matrix with random far-apart off-diagonals (many
+    distinct column offsets)."""
+    rng = np.random.default_rng(seed)
+    i = np.repeat(np.arange(n), per_row)
+    j = rng.integers(0, n, size=n * per_row)
+    keep = i != j
+    i, j = i[keep], j[keep]
+    v = -rng.uniform(0.1, 1.0, size=i.size)
+    rows = np.concatenate([i, j])
+    cols = np.concatenate([j, i])
+    vals = np.concatenate([v, v])
+    key = rows * n + cols
+    uniq, inv = np.unique(key, return_inverse=True)
+    acc = np.zeros(uniq.size)
+    np.add.at(acc, inv, vals)
+    r, c = uniq // n, uniq % n
+    diag = np.zeros(n)
+    np.add.at(diag, r, -acc)
+    r = np.concatenate([r, np.arange(n)])
+    c = np.concatenate([c, np.arange(n)])
+    v = np.concatenate([acc, diag + rng.uniform(0.5, 1.0, n)])
+    order = np.lexsort((c, r))
+    r, c, v = r[order], c[order], v[order]
+    row_ptr = np.zeros(n + 1, dtype=np.int64)
+    np.add.at(row_ptr, r + 1, 1)
+    return fi.CSR(n, np.cumsum(row_ptr), c.astype(np.int32), v.astype(np.float32))
+
+
+@pytest.mark.parametrize("kind,R,prec", [("lap", 8, fth.FTH_FP32), ("lap", 32, fth.FTH_FP64),
+                                         ("band", 32, fth.FTH_FP32), ("band", 8, fth.FTH_FP64)])
+def test_coded_matrix_bit_identical_to_plain_csr(kind, R, prec):
+    """The coded form (one-byte column and value codes into tables, slots in
+    CSR order) sums the same products in the same order: bit-identical."""
+    M = fi.laplacian3d_csr(20, 0.1) if kind == "lap" else fi.banded_spd_csr(40_000, 9)
+    h = fi.dt_rule(fi.laplacian3d_lambda_max(20, 0.1) if kind == "lap" else fi.gershgorin_max(M))
+    g = fi.load_gle("invsqrt_ns4")
+    kw = dict(pairs=fi.random_pairs(M.n, 64, 2), replicas=R, precision=prec, seed=5, acc_diag=True, block_len=7,
+              temporal_steps=-1, steps_per_graph=16)
+    a = fth.Solver(M, g.A_p, g.C_p, h, **kw).run(3).run(70)
+    b = fth.Solver(M, g.A_p, g.C_p, h, coded_matrix=-1, **kw).run(3).run(70)
+    print(f"[coded] {a.kernel_name} | {b.kernel_name}", flush=True)
+    assert "CODED=1" in a.kernel_name and "CODED=0" in b.kernel_name
+    for x, y in zip(a.state(), b.state()):
+        assert np.array_equal(x, y)
+    for x, y in zip(a.accumulators()[:3], b.accumulators()[:3]):
+        assert np.array_equal(x, y)
+
+
+def test_coded_matrix_not_built_for_scattered_patterns():
+    M = random_symmetric_csr(3000, 1, 4)
+    assert np.diff(M.row_ptr).max() <= 8
+    g = fi.load_gle("invsqrt_ns4")
+    h = fi.dt_rule(fi.gershgorin_max(M))
+    a = fth.Solver(M, g.A_p, g.C_p, h, replicas=8, seed=1).run(20)
+    assert "CODED=0" in a.kernel_name   # far more than 255 distinct offsets j - i
+    b = fth.Solver(M, g.A_p, g.C_p, h, replicas=8, seed=1, coded_matrix=-1).run(20)
+    for x, y in zip(a.state(), b.state()):
+        assert np.array_equal(x, y)
