@@ -58,7 +58,7 @@ def lib():
         L.orc_normal.restype = ctypes.c_double
         L.orc_normals.argtypes = [u64, u32, i64, P, P, P, P, P]
         L.orc_run.argtypes = [i64, ctypes.c_int, P, P, P, P, ctypes.c_int, P, P, ctypes.c_double,
-                              i64, u64, u32, i64, i64, i64, i64, P, P, P, i64, P, P, P, P, P,
+                              i64, u64, u32, i64, i64, i64, i64, P, P, P, i64, P, P, P, P, P, P,
                               ctypes.c_int]
         L.orc_run.restype = ctypes.c_int
         L.orc_max_threads.restype = ctypes.c_int
@@ -158,11 +158,13 @@ class OracleRun:
 
     ``M`` is either a dense ndarray [N, N] or an object with ``n``,
     ``row_ptr``, ``col``, ``val`` (CSR).  Values are used in float64.
-    ``pairs`` is int32 [A, 2]; diagonal entries are pairs (i, i).
+    ``pairs`` is int32 [A, 2]; diagonal entries are pairs (i, i).  With
+    ``pp=True`` every pair is accumulated twice: first as <q_i q_j>, then (in
+    a second block of the same order) as the momentum form <p_i p_j> of Eq. 7.
     """
 
     def __init__(self, M, A_p, C_p, h, R, pairs, seed=0, stream=0, burn_in=0,
-                 block_len=100, T=None, S=None, nthreads=0):
+                 block_len=100, T=None, S=None, nthreads=0, pp=False):
         if isinstance(M, np.ndarray):
             self.fmt = 0
             self.N = M.shape[0]
@@ -193,7 +195,10 @@ class OracleRun:
         self.q = np.zeros((N, R))
         self.p = np.zeros((N, R))
         self.s = np.zeros((ns, N, R))
-        self.pairs = np.ascontiguousarray(np.asarray(pairs, dtype=np.int32).reshape(-1, 2))
+        base = np.asarray(pairs, dtype=np.int32).reshape(-1, 2)
+        self.pairs = np.ascontiguousarray(np.concatenate([base, base]) if pp else base)
+        self.kinds = np.ascontiguousarray(np.repeat(np.array([0, 1], dtype=np.int32) if pp else np.zeros(1, np.int32),
+                                                    len(base)))
         A = len(self.pairs)
         self.blk = np.zeros(A)
         self.s1 = np.zeros(A)
@@ -214,7 +219,7 @@ class OracleRun:
                            _ptr(self.val), self.ns, _ptr(self.T), _ptr(self.S), self.h, self.R,
                            self.seed, self.stream, self.step, int(nsteps), self.burn_in, self.L,
                            _ptr(self.q), _ptr(self.p), _ptr(self.s), len(self.pairs),
-                           _ptr(self.pairs), _ptr(self.blk), _ptr(self.s1), _ptr(self.s2),
+                           _ptr(self.pairs), _ptr(self.kinds), _ptr(self.blk), _ptr(self.s1), _ptr(self.s2),
                            _ptr(self.nblocks), self.nthreads)
         if rc != 0:
             raise MemoryError("oracle allocation failed")

@@ -126,6 +126,16 @@ def gh(lam, A_p, C_p, h, T=None, S=None) -> np.ndarray:
     return np.array([gh_cov(float(l), T, S, h)[0, 0] for l in lam])
 
 
+def gh_p(lam, A_p, C_p, h, T=None, S=None) -> np.ndarray:
+    """Exact stationary <p^2> of the integrated discrete dynamics at the
+    step boundary (p_n, the instant q_n is sampled), at omega^2 = lam: the
+    response behind the momentum form of the estimator (Eq. 7)."""
+    if T is None or S is None:
+        T, S = propagator(A_p, C_p, h)
+    lam = _as_arr(lam)
+    return np.array([gh_cov(float(l), T, S, h)[1, 1] for l in lam])
+
+
 def spectral_radius(lam: float, T: np.ndarray, S: np.ndarray, h: float) -> float:
     G, _ = step_map(lam, T, S, h)
     return float(np.max(np.abs(np.linalg.eigvals(G))))
@@ -151,6 +161,11 @@ def matrix_function(M: np.ndarray, g_of_lam) -> np.ndarray:
 def gh_matrix(M, A_p, C_p, h) -> np.ndarray:
     T, S = propagator(A_p, C_p, h)
     return matrix_function(M, lambda lam: gh(lam, A_p, C_p, h, T, S))
+
+
+def gh_p_matrix(M, A_p, C_p, h) -> np.ndarray:
+    T, S = propagator(A_p, C_p, h)
+    return matrix_function(M, lambda lam: gh_p(lam, A_p, C_p, h, T, S))
 
 
 def g0_matrix(M, A_p, C_p) -> np.ndarray:

@@ -125,12 +125,15 @@ void orc_philox_batch(int64_t count, const uint32_t* ctr, const uint32_t* key, u
  *   blk  = sum of x over the current (incomplete) block,
  *   s1   = sum over completed blocks of the block sums,
  *   s2   = sum over completed blocks of the squared block sums,
- * where x(n) = sum_r q_i^r(n) q_j^r(n) for every n >= burn_in; a block closes
- * after the step with (n - burn_in + 1) % L == 0 and then *nblocks grows by one.
+ * where x(n) = sum_r q_i^r(n) q_j^r(n) for every n >= burn_in, or, for a pair
+ * with kinds[k] == 1, the momentum form sum_r p_i^r(n) p_j^r(n) of Eq. 7
+ * (p_n, the momentum at the start of step n, the same instant as q_n); kinds
+ * may be NULL (all position pairs).  A block closes after the step with
+ * (n - burn_in + 1) % L == 0 and then *nblocks grows by one.
  *
  * One step n (all dofs and replicas):
  *   1. F = -M q_n
- *   2. accumulate x(n) from q_n
+ *   2. accumulate x(n) from q_n (or p_n)
  *   3. p += (h/2) F
  *   4. (p, s) <- T (p, s) + S xi(n)
  *   5. p += (h/2) F
@@ -141,7 +144,7 @@ int orc_run(int64_t N, int fmt, const double* dense, const int64_t* row_ptr,
             const int32_t* col, const double* val, int ns, const double* T,
             const double* S, double h, int64_t R, uint64_t seed, uint32_t stream,
             int64_t n0, int64_t nsteps, int64_t burn_in, int64_t L, double* q,
-            double* p, double* s, int64_t npairs, const int32_t* pairs, double* blk,
+            double* p, double* s, int64_t npairs, const int32_t* pairs, const int32_t* kinds, double* blk,
             double* s1, double* s2, int64_t* nblocks, int nthreads)
 {
 #ifdef _OPENMP
@@ -175,15 +178,16 @@ int orc_run(int64_t N, int fmt, const double* dense, const int64_t* row_ptr,
             }
         }
 
-        /* 2. accumulate <q_i q_j> from q_n */
+        /* 2. accumulate <q_i q_j> from q_n (<p_i p_j> from p_n) */
         if (n >= burn_in && npairs > 0) {
             const int close = ((n - burn_in + 1) % L) == 0;
             #pragma omp parallel for schedule(static) if(npairs * R >= 16384)
             for (int64_t k = 0; k < npairs; ++k) {
                 const int64_t a = pairs[2 * k], b = pairs[2 * k + 1];
+                const double* v = (kinds && kinds[k] == 1) ? p : q;
                 double x = 0.0;
                 for (int64_t r = 0; r < R; ++r)
-                    x += q[a * R + r] * q[b * R + r];
+                    x += v[a * R + r] * v[b * R + r];
                 blk[k] += x;
                 if (close) {
                     s1[k] += blk[k];

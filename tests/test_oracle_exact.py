@@ -114,3 +114,32 @@ def test_lanczos_quadratic_form_matches_eigh():
             val = 0.25 * (exact.lanczos_quadratic_form(mv, 300, e_i + e_j, g, 120)
                           - exact.lanczos_quadratic_form(mv, 300, e_i - e_j, g, 120))
         assert val == pytest.approx(ref[i, j], abs=1e-10)
+
+
+def test_gh_p_white_noise_closed_form():
+    """The step boundary lies between the drift and the first kick of a
+    velocity-Verlet block.  Before that block (p, q) follow the Gibbs law of
+    the conserved p^2/2 + omega^2 (1 - h^2 omega^2/4) q^2/2 (p ~ N(0, kT)); the
+    half kick p - (h/2) omega^2 q then has variance kT / (1 - h^2 omega^2 / 4)."""
+    h = 0.3
+    lam = np.geomspace(0.05, 30.0, 13)
+    for gamma in (0.2, 1.0, 5.0):
+        got = exact.gh_p(lam, [[gamma]], [[1.7]], h)
+        assert np.allclose(got, 1.7 / (1 - h * h * lam / 4), rtol=1e-10)
+
+
+def test_g0_p_is_omega_squared_times_g0():
+    """A stationary harmonic mode has d<q p>/dt = <p^2> - omega^2 <q^2> = 0, so
+    <p^2>(omega) = omega^2 <q^2>(omega) for any GLE (continuous time)."""
+    A, C = gle(4, 9)
+    lam = np.geomspace(0.1, 12, 9)
+    assert np.allclose(exact.g0_p(lam, A, C), lam * exact.g0(lam, A, C), rtol=1e-9)
+
+
+def test_gh_p_converges_to_g0_p_second_order():
+    A, C = gle(4, 11)
+    lam = np.array([0.3, 2.0, 9.0])
+    e1 = np.abs(exact.gh_p(lam, A, C, 0.02) - exact.g0_p(lam, A, C))
+    e2 = np.abs(exact.gh_p(lam, A, C, 0.01) - exact.g0_p(lam, A, C))
+    ratio = e1 / e2
+    assert np.all((ratio > 3.5) & (ratio < 4.5)), ratio

@@ -206,3 +206,43 @@ def test_stderr_calibration_over_seeds(orc):
         ses.append(s)
     ratio = np.std(means, axis=0, ddof=1) / np.mean(ses, axis=0)
     assert np.all((ratio > 0.65) & (ratio < 1.5)), ratio
+
+
+def test_momentum_form_white_noise_closed_form(orc):
+    """Momentum form of the estimator (Eq. 7, p_n sampled with q_n): with a
+    white-noise thermostat the integrated step samples <p p^T> =
+    kT (I - h^2 M / 4)^-1 exactly; the continuous-time kT I is excluded at
+    this h.  The q-q block of the same run is unchanged by keeping p-p."""
+    N, R = 6, 256
+    M, lam = random_spd(N, 22, 1.0, 10.0)
+    h = 0.9 / np.sqrt(lam.max())
+    kT = 1.3
+    pairs = np.array([(i, j) for i in range(N) for j in range(i, N)], dtype=np.int32)
+    run = oracle.OracleRun(M, [[1.0]], [[kT]], h, R, pairs, seed=35, burn_in=400, block_len=100, pp=True)
+    run.run(6400)
+    mean, se = run.estimates()
+    A = len(pairs)
+    ref_h = (kT * np.linalg.inv(np.eye(N) - h * h * M / 4))[pairs[:, 0], pairs[:, 1]]
+    ref_0 = (kT * np.eye(N))[pairs[:, 0], pairs[:, 1]]
+    z = (mean[A:] - ref_h) / se[A:]
+    assert np.max(np.abs(z)) < 4.5, z
+    assert np.max(np.abs((mean[A:] - ref_0) / se[A:])) > 6.0
+    q_only = oracle.OracleRun(M, [[1.0]], [[kT]], h, R, pairs, seed=35, burn_in=400, block_len=100).run(6400)
+    assert np.array_equal(q_only.s1, run.s1[:A]) and np.array_equal(q_only.blk, run.blk[:A])
+
+
+def test_momentum_form_fitted_gle_matches_exact(orc):
+    """Colored noise: time averages of p_i p_j approach U gh_p(Lambda) U^T,
+    the exact stationary momentum response of the integrated step."""
+    g = fth_inputs.load_gle("invsqrt_ns4")
+    N, R = 5, 128
+    M, lam = random_spd(N, 43, 0.2, 10.0)
+    h = 0.1 / np.sqrt(lam.max())
+    pairs = np.array([(i, j) for i in range(N) for j in range(i, N)], dtype=np.int32)
+    run = oracle.OracleRun(M, g.A_p, g.C_p, h, R, pairs, seed=36, burn_in=2000, block_len=400, pp=True)
+    run.run(12000)
+    mean, se = run.estimates()
+    A = len(pairs)
+    ref = exact.gh_p_matrix(M, g.A_p, g.C_p, h)[pairs[:, 0], pairs[:, 1]]
+    z = (mean[A:] - ref) / se[A:]
+    assert np.max(np.abs(z)) < 4.5, z
