@@ -132,6 +132,9 @@ typedef struct {
                                 the distinct offsets and, if <= 256, distinct values) that the
                                 one-step kernel reads for R >= 4; -1: plain CSR only.  Results
                                 are identical either way. */
+    int32_t acc_pp;          /* != 0: also accumulate <p_i p_j> (the momentum form of Eq. 7:
+                                p_n sampled with q_n) for the same pairs and diagonal; the
+                                estimates then come in two blocks, q-q then p-p */
 } fth_options;
 
 /* Fill *opt with defaults: seed 0, stream 0, FTH_FP32, burn_in 0,
@@ -157,10 +160,11 @@ fth_status fth_create(const fth_matrix* M, const fth_gle* gle, double dt,
 fth_status fth_run(fth_ctx* ctx, int64_t nsteps, int32_t replicas);
 
 /* Number of estimates: npairs, plus n when acc_diag (pairs first, in input
- * order, then the diagonal in index order). */
+ * order, then the diagonal in index order); twice that with acc_pp, the q-q
+ * block followed by the p-p block in the same order. */
 int64_t fth_num_outputs(const fth_ctx* ctx);
 
-/* Estimates of <q_i q_j> and their standard errors (len >= fth_num_outputs,
+/* Estimates of <q_i q_j> (and <p_i p_j> with acc_pp) and their standard errors (len >= fth_num_outputs,
  * else FTH_EINVAL).  mean = (sum of all accumulated samples) / (R n_acc);
  * stderr from the complete blocks (+inf with fewer than two).  Either output
  * pointer may be NULL.  *nsamples (if not NULL) receives n_acc, the number of

@@ -38,7 +38,7 @@ __device__ __forceinline__ void csr_row(const StepArgs<Real>& a, const StepInfo&
     // per SIMD), which measured faster than eight entries at 92-114 VGPRs
     constexpr int G = 4;
     const int64_t kb = a.row_ptr[i], ke = a.row_ptr[i + 1];
-    const RowState<Real, NS, RPT> st = load_row<Real, NS, RPT, NT>(a, qr, i, si.r0);
+    const RowState<Real, NS, RPT> st = load_row<Real, NS, RPT, NT>(a, si, qr, i);
     V qj[G];
     Real vj[G];
 #pragma unroll
@@ -92,7 +92,7 @@ __device__ __forceinline__ void coded_row(const StepArgs<Real>& a, const StepInf
     constexpr int G = 4;  // slots gathered per batch (two batches)
     const uint64_t cc = a.ell_col[i];
     const uint64_t vc = a.ell_vcode != nullptr ? a.ell_vcode[i] : 0;
-    const RowState<Real, NS, RPT> st = load_row<Real, NS, RPT, NT>(a, qr, i, si.r0);
+    const RowState<Real, NS, RPT> st = load_row<Real, NS, RPT, NT>(a, si, qr, i);
     auto value = [&](int u) -> Real {
         return a.ell_vcode != nullptr ? s_val[(vc >> (8 * u)) & 255u] : a.ell_vraw[i * kCodedSlots + u];
     };

@@ -253,7 +253,7 @@ __global__ __launch_bounds__(256) void dense_epilogue_kernel(const StepArgs<Real
     const int64_t i = t * per_block + si.slot;
     if (i >= a.N) return;
 
-    const RowState<Real, NS, RPT> st = load_row<Real, NS, RPT, NT>(a, qr, i, si.r0);
+    const RowState<Real, NS, RPT> st = load_row<Real, NS, RPT, NT>(a, si, qr, i);
     constexpr int KMAX = 8;
     V pv[KMAX];
 #pragma unroll

@@ -348,7 +348,8 @@ fth_status ensure_state(fth_ctx* c, int32_t R) {
     if (c->dense() && !c->m_uploaded) {
         const int64_t threads = c->n * (R / std::min(R, 4));
         const size_t rb = c->real_bytes();
-        const size_t lds_base = size_t(c->npairs + (c->opt.acc_diag ? c->n : 0)) * 8 + 2 * size_t(c->n) * R * rb;
+        const size_t lds_base = size_t(c->n_out()) * 8 + 2 * size_t(c->n) * R * rb *
+                                (c->opt.acc_pp && c->npairs > 0 ? 2 : 1);
         const bool small = c->n * R <= kSmallMaxNR && R <= 64 && threads <= 1024 && lds_base <= kSmallMaxLds;
         fth_status st2;
         if (small) {
@@ -381,10 +382,12 @@ fth_status ensure_state(fth_ctx* c, int32_t R) {
     c->nt = st * size_t(c->ns + 3) > (size_t(128) << 20);
     HIP_OK(c->dalloc(&c->d_q[0], qst));
     HIP_OK(c->dalloc(&c->d_q[1], qst));
-    HIP_OK(c->dalloc(&c->d_ps, c->ps_bytes()));
+    HIP_OK(c->dalloc(&c->d_ps[0], c->ps_bytes()));
+    HIP_OK(c->dalloc(&c->d_ps[1], c->ps_bytes()));
     HIP_OK(hipMemsetAsync(c->d_q[0], 0, qst, c->stream));
     HIP_OK(hipMemsetAsync(c->d_q[1], 0, qst, c->stream));
-    HIP_OK(hipMemsetAsync(c->d_ps, 0, c->ps_bytes(), c->stream));
+    HIP_OK(hipMemsetAsync(c->d_ps[0], 0, c->ps_bytes(), c->stream));
+    HIP_OK(hipMemsetAsync(c->d_ps[1], 0, c->ps_bytes(), c->stream));
     if (c->mfma()) {
         const size_t pb = size_t(c->ksplit) * size_t(c->rows_pad) * size_t(R) * rb;
         HIP_OK(c->dalloc(&c->d_part, pb));
@@ -421,7 +424,9 @@ fth::StepArgs<Real> step_args(fth_ctx* c) {
     a.m_in_lds = c->small_m_in_lds;
     a.q0 = static_cast<Real*>(c->d_q[0]);
     a.q1 = static_cast<Real*>(c->d_q[1]);
-    a.ps = static_cast<Real*>(c->d_ps);
+    a.ps = static_cast<Real*>(c->d_ps[0]);
+    a.ps_b = static_cast<Real*>(c->d_ps[1]);
+    a.ns = c->ns;
     a.ps_lg = c->ps_lg;
     a.TS = static_cast<const Real*>(c->d_TS);
     a.h = Real(c->h);
@@ -448,6 +453,17 @@ fth::StepArgs<Real> step_args(fth_ctx* c) {
         a.dblk = blk + c->npairs;
         a.ds1 = s1 + c->npairs;
         a.ds2 = s2 + c->npairs;
+    }
+    if (c->opt.acc_pp) {  // the p-p block follows the q-q block
+        const int64_t o = c->n_kind();
+        a.pp_blk = blk + o;
+        a.pp_s1 = s1 + o;
+        a.pp_s2 = s2 + o;
+        if (c->opt.acc_diag) {
+            a.dp_blk = blk + o + c->npairs;
+            a.dp_s1 = s1 + o + c->npairs;
+            a.dp_s2 = s2 + o + c->npairs;
+        }
     }
     a.flag = c->d_flag;
     const int per_block = c->block / (c->R / c->rpt);
@@ -525,9 +541,8 @@ bool tb_eligible(const fth_ctx* c, int KT, int block) {
 }
 
 fth_status tb_prepare(fth_ctx* c) {
-    if (c->d_ps_alt) return FTH_OK;
+    if (c->d_snap || c->d_pair_slot) return FTH_OK;
     const size_t rb = c->real_bytes();
-    HIP_OK(c->dalloc(&c->d_ps_alt, c->ps_bytes()));
     if (c->npairs > 0) {
         std::vector<int32_t> pairs(size_t(2 * c->npairs));
         HIP_OK(hipMemcpy(pairs.data(), c->d_pairs, sizeof(int32_t) * pairs.size(), hipMemcpyDeviceToHost));
@@ -544,13 +559,12 @@ fth_status tb_prepare(fth_ctx* c) {
         HIP_OK(hipMemcpy(c->d_pair_slot, slot.data(), sizeof(int32_t) * slot.size(), hipMemcpyHostToDevice));
         HIP_OK(c->dalloc(reinterpret_cast<void**>(&c->d_pair_slots), sizeof(int32_t) * pslots.size()));
         HIP_OK(hipMemcpy(c->d_pair_slots, pslots.data(), sizeof(int32_t) * pslots.size(), hipMemcpyHostToDevice));
-        HIP_OK(c->dalloc(&c->d_snap, size_t(kTbMaxSteps) * size_t(ns) * size_t(c->R) * rb));
+        HIP_OK(c->dalloc(&c->d_snap, size_t(kTbMaxSteps) * 2 * size_t(ns) * size_t(c->R) * rb));
     }
     return FTH_OK;
 }
 
 void tb_release(fth_ctx* c) {
-    c->dfree(c->d_ps_alt);
     c->dfree(reinterpret_cast<void*&>(c->d_pair_slot));
     c->dfree(reinterpret_cast<void*&>(c->d_pair_slots));
     c->dfree(c->d_snap);
@@ -558,8 +572,7 @@ void tb_release(fth_ctx* c) {
     c->tb_kt = 0;
 }
 
-// Blocked launch j of a chunk: steps [j KT, j KT + KT) of it; (p, s) moves
-// from one buffer to the other, so launches come in pairs.
+// Blocked launch j of a chunk: steps [j KT, j KT + KT) of it.
 template <typename Real>
 fth_status enqueue_tb(fth_ctx* c, int j) {
     fth::StepArgs<Real> a = step_args<Real>(c);
@@ -567,10 +580,6 @@ fth_status enqueue_tb(fth_ctx* c, int j) {
     tb.E = c->tb_block / (c->R / 4);
     tb.w = int32_t(c->band_w);
     tb.T = tb.E - 2 * c->tb_kt * tb.w;
-    Real* ps0 = static_cast<Real*>(c->d_ps);
-    Real* ps1 = static_cast<Real*>(c->d_ps_alt);
-    tb.ps_in = (j & 1) ? ps1 : ps0;
-    tb.ps_out = (j & 1) ? ps0 : ps1;
     tb.pair_slot = c->d_pair_slot;
     tb.snap = static_cast<Real*>(c->d_snap);
     tb.nslots = c->tb_nslots;
@@ -588,7 +597,7 @@ fth_status enqueue_tb(fth_ctx* c, int j) {
 fth_status enqueue_chunk(fth_ctx* c, int K) {
     int k0 = 0;
     if (c->tb_kt > 0) {
-        const int nl = 2 * (K / (2 * c->tb_kt));
+        const int nl = K / c->tb_kt;
         for (int j = 0; j < nl; ++j) {
             fth_status st = c->prec == FTH_FP64 ? enqueue_tb<double>(c, j) : enqueue_tb<float>(c, j);
             if (st != FTH_OK) return st;
@@ -692,7 +701,7 @@ fth_status autotune(fth_ctx* c) {
         std::vector<void*> p;
         ~Saved() { for (void* x : p) (void)hipFree(x); }
     } sv;
-    void* bufs[4] = {c->d_q[0], c->d_q[1], c->d_ps, c->d_acc};
+    void* bufs[4] = {c->d_q[0], c->d_q[1], c->d_ps[c->step & 1], c->d_acc};
     const size_t sizes[4] = {qb, qb, psb, std::max<size_t>(ab, 8)};
     for (int k = 0; k < 4; ++k) {
         void* x = nullptr;
@@ -733,7 +742,7 @@ fth_status autotune(fth_ctx* c) {
                 c->tb_kt = kt;
                 c->tb_block = tbb;
                 double us = 0.0;
-                st = time_chunk(c, 4 * kt, &us);
+                st = time_chunk(c, 2 * kt, &us);
                 if (st != FTH_OK) return st;
                 if (us < best.us) best = TuneChoice{best4.block, 4, best4.nt, us, kt, tbb};
             }
@@ -750,7 +759,7 @@ fth_status autotune(fth_ctx* c) {
     c->tuned_us = best.us;
     c->tb_kt = best.tb_kt;
     c->tb_block = best.tb_kt > 0 ? best.tb_block : 1024;
-    if (best.tb_kt == 0 && c->d_ps_alt) tb_release(c);
+    if (best.tb_kt == 0) tb_release(c);
     if (c->gexec) {
         (void)hipGraphExecDestroy(c->gexec);
         c->gexec = nullptr;
@@ -762,7 +771,7 @@ fth_status autotune(fth_ctx* c) {
 fth_status run_enqueue(fth_ctx* c, int64_t nsteps) {
     fth_status st;
     int K = c->opt.steps_per_graph > 0 ? c->opt.steps_per_graph : kDefaultGraphSteps;
-    if (c->tb_kt > 0) K = (K + 2 * c->tb_kt - 1) / (2 * c->tb_kt) * (2 * c->tb_kt);  // whole launch pairs
+    if (c->tb_kt > 0) K = (K + c->tb_kt - 1) / c->tb_kt * c->tb_kt;  // whole blocked launches
     if (c->d_qt && c->qt_dirty) {
         if (fth::launch_qt_from_q(static_cast<const float*>(c->d_q[c->step & 1]), c->d_qt, c->n, c->rows_pad, c->R,
                                   c->stream) != 0)
@@ -840,12 +849,12 @@ size_t fth_footprint_bytes(const fth_matrix* M, int32_t ns, int32_t R, int64_t n
     size_t bytes = 0;
     if (M->format == FTH_CSR) {
         bytes += (n + 1) * 8 + size_t(M->nnz) * (4 + rb);
-        bytes += n * size_t(R) * rb * 2 + ps_rows * size_t(R) * rb * size_t(1 + ns);
+        bytes += n * size_t(R) * rb * 2 + 2 * ps_rows * size_t(R) * rb * size_t(1 + ns);
     } else {
         const size_t P = (n + 255) / 256 * 256;
         const size_t ks = P >= 2048 ? 8 : P / 256;
         bytes += P * P * (precision == FTH_FP32_BF16X3 ? 4 : rb);           // M (hi + lo, or FP64)
-        bytes += 2 * P * size_t(R) * rb + ps_rows * size_t(R) * rb * size_t(1 + ns);  // q pair (padded), p and s
+        bytes += 2 * P * size_t(R) * rb + 2 * ps_rows * size_t(R) * rb * size_t(1 + ns);  // q, (p, s) pairs
         bytes += ks * P * size_t(R) * rb;                                      // split-K partials
         if (precision == FTH_FP32_BF16X3) bytes += P * size_t(R) * 4;          // bf16 q split
     }
@@ -875,6 +884,7 @@ fth_status fth_create(const fth_matrix* M, const fth_gle* gle, double dt, const 
         opt.temporal_threads != 1024)
         return fail(FTH_EINVAL, "temporal_threads must be 0, 256, 512 or 1024");
     if (opt.coded_matrix != 0 && opt.coded_matrix != -1) return fail(FTH_EINVAL, "coded_matrix must be 0 or -1");
+    if (opt.acc_pp != 0 && opt.acc_pp != 1) return fail(FTH_EINVAL, "acc_pp must be 0 or 1");
     if (npairs < 0 || (npairs > 0 && !pairs)) return fail(FTH_EINVAL, "invalid pair list");
     for (int64_t k = 0; k < 2 * npairs; ++k)
         if (pairs[k] < 0 || pairs[k] >= M->n) return fail(FTH_EINVAL, "pair index out of range at %lld", (long long)k);
@@ -1056,11 +1066,11 @@ fth_status fth_get_state(fth_ctx* c, double* q, double* p, double* s) {
     std::vector<double> qh(cnt), psh(pscnt);
     if (c->prec == FTH_FP64) {
         HIP_OK(hipMemcpy(qh.data(), c->d_q[c->step & 1], sizeof(double) * cnt, hipMemcpyDeviceToHost));
-        HIP_OK(hipMemcpy(psh.data(), c->d_ps, sizeof(double) * pscnt, hipMemcpyDeviceToHost));
+        HIP_OK(hipMemcpy(psh.data(), c->d_ps[c->step & 1], sizeof(double) * pscnt, hipMemcpyDeviceToHost));
     } else {
         std::vector<float> tq(cnt), tps(pscnt);
         HIP_OK(hipMemcpy(tq.data(), c->d_q[c->step & 1], sizeof(float) * cnt, hipMemcpyDeviceToHost));
-        HIP_OK(hipMemcpy(tps.data(), c->d_ps, sizeof(float) * pscnt, hipMemcpyDeviceToHost));
+        HIP_OK(hipMemcpy(tps.data(), c->d_ps[c->step & 1], sizeof(float) * pscnt, hipMemcpyDeviceToHost));
         for (size_t k = 0; k < cnt; ++k) qh[k] = tq[k];
         for (size_t k = 0; k < pscnt; ++k) psh[k] = tps[k];
     }
@@ -1098,10 +1108,10 @@ fth_status fth_set_state(fth_ctx* c, const double* q, const double* p, const dou
         const size_t pscnt = c->ps_bytes() / rb;
         std::vector<double> psh(pscnt);
         if (f64) {
-            HIP_OK(hipMemcpy(psh.data(), c->d_ps, sizeof(double) * pscnt, hipMemcpyDeviceToHost));
+            HIP_OK(hipMemcpy(psh.data(), c->d_ps[c->step & 1], sizeof(double) * pscnt, hipMemcpyDeviceToHost));
         } else {
             std::vector<float> t(pscnt);
-            HIP_OK(hipMemcpy(t.data(), c->d_ps, rb * pscnt, hipMemcpyDeviceToHost));
+            HIP_OK(hipMemcpy(t.data(), c->d_ps[c->step & 1], rb * pscnt, hipMemcpyDeviceToHost));
             for (size_t k = 0; k < pscnt; ++k) psh[k] = t[k];
         }
         for (size_t i = 0; i < size_t(c->n); ++i)
@@ -1111,7 +1121,7 @@ fth_status fth_set_state(fth_ctx* c, const double* q, const double* p, const dou
                     for (size_t k = 0; k + 1 < D; ++k)
                         psh[c->ps_offset(int64_t(i), int(k + 1), int(r))] = s[(k * size_t(c->n) + i) * R + r];
             }
-        HIP_OK(put(c->d_ps, psh));
+        HIP_OK(put(c->d_ps[c->step & 1], psh));
     }
     return FTH_OK;
 }

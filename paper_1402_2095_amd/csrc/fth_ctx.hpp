@@ -45,7 +45,8 @@ struct fth_ctx {
     std::vector<double> m_host;  // dense M kept until R fixes the path (n <= 4096)
     bool m_uploaded = false;
     void* d_q[2] = {nullptr, nullptr};
-    void* d_ps = nullptr;  // p then s_1..s_ns, rows grouped by 2^ps_lg (see ps_offset)
+    void* d_ps[2] = {nullptr, nullptr};  // p then s_1..s_ns, ping-pong by step parity,
+                                         // rows grouped by 2^ps_lg (see ps_offset)
     int ps_lg = 0;         // log2 of rows per (p, s) group
     int64_t ps_rows = 0;   // n rounded up to whole groups
     double* d_acc = nullptr;  // [3][n_out]: blk, s1, s2 (pairs first, then diagonal)
@@ -64,10 +65,9 @@ struct fth_ctx {
     int max_row_nnz = 0;   // longest CSR row
     int tb_kt = 0;         // steps per blocked launch, 0: one-step kernels
     int tb_block = 1024;   // threads per blocked workgroup
-    void* d_ps_alt = nullptr;          // second (p, s) buffer: blocked launches ping-pong
     int32_t* d_pair_slot = nullptr;    // [n]: snapshot slot of a row in a pair, or -1
     int32_t* d_pair_slots = nullptr;   // [npairs][2]
-    void* d_snap = nullptr;            // [kTbMaxSteps][nslots][R]
+    void* d_snap = nullptr;            // [kTbMaxSteps][2][nslots][R]
     int64_t tb_nslots = 0;
     // schedule
     int R = 0;
@@ -98,7 +98,9 @@ struct fth_ctx {
     bool dense() const { return fmt == FTH_DENSE; }
     bool mfma() const { return dense() && !small; }
     int64_t q_rows() const { return mfma() ? rows_pad : n; }
-    int64_t n_out() const { return npairs + (opt.acc_diag ? n : 0); }
+    // accumulated estimates: q-q pairs, q-q diagonal, then the same for p-p if kept
+    int64_t n_kind() const { return npairs + (opt.acc_diag ? n : 0); }
+    int64_t n_out() const { return n_kind() * (opt.acc_pp ? 2 : 1); }
     size_t ps_bytes() const { return size_t(ps_rows) * size_t(R) * size_t(ns + 1) * real_bytes(); }
     // element offset of (row i, component c, replica r) in the (p, s) buffer:
     // groups of 2^ps_lg rows, each component of a group a contiguous [2^ps_lg][R] block

@@ -37,11 +37,13 @@ struct StepArgs {
     // small dense systems: M [N][N] row-major in state precision; kept in LDS if m_in_lds
     const Real* mdense;
     int32_t m_in_lds;
-    // state: q ping-pong [rows][R]; p and s in groups of 2^ps_lg rows, component-major
+    // state: q ping-pong [rows][R]; (p, s) ping-pong as well (step n reads buffer
+    // n & 1 and writes the other), each in groups of 2^ps_lg rows, component-major
     // inside a group: ps[row >> ps_lg][ns+1][row & (2^ps_lg - 1)][R] (p is component 0)
     Real* q0;
     Real* q1;
-    Real* ps;
+    Real* ps;    // buffer 0
+    Real* ps_b;  // buffer 1
     int32_t ps_lg;
     // propagator T then S, each (ns+1)^2 row-major, state precision
     const Real* TS;
@@ -65,10 +67,20 @@ struct StepArgs {
     double* pblk;
     double* ps1;
     double* ps2;
+    // p-p accumulators (p_n, sampled with q_n) for the same pairs and diagonal; null if not kept
+    double* pp_blk;
+    double* pp_s1;
+    double* pp_s2;
+    double* dp_blk;
+    double* dp_s1;
+    double* dp_s2;
     int32_t* flag;  // set to 1 when a non-finite state value appears
+    int32_t ns;     // extra GLE momenta
     // launch geometry
     int64_t row_tiles;         // tiles of rows
     int64_t row_tiles_padded;  // rounded up to a multiple of 8 (XCD remap)
+
+    __host__ __device__ int D() const { return ns + 1; }
 };
 
 // Launch shape of a step kernel.
@@ -105,7 +117,7 @@ struct DenseGemmArgs {
 // entries stay in registers for the whole launch, so larger NS (and FP64)
 // need the register file of fewer threads.
 constexpr int tb_max_block(bool f64, int ns) {
-    return f64 ? (ns <= 1 ? 1024 : ns <= 4 ? 512 : 256) : (ns <= 5 ? 1024 : 512);
+    return f64 ? (ns == 0 ? 1024 : ns <= 4 ? 512 : 256) : (ns <= 4 ? 1024 : ns <= 9 ? 512 : 256);
 }
 
 // Extra arguments of the temporally blocked sparse step.
@@ -114,10 +126,8 @@ struct TbArgs {
     int32_t E;                 // extended rows per workgroup
     int32_t T;                 // output rows per workgroup
     int32_t w;                 // half-bandwidth of M
-    const Real* ps_in;         // (p, s) before the launch
-    Real* ps_out;              // (p, s) after the launch (the other buffer)
     const int32_t* pair_slot;  // [N]: snapshot slot of a row used by a pair, or -1
-    Real* snap;                // [KT][nslots][R]: q of pair rows at each step
+    Real* snap;                // [KT][2][nslots][R]: q (and p, if kept) of pair rows at each step
     int64_t nslots;
     const int32_t* pair_slots; // [npairs][2]: snapshot slots of each pair's rows
 };

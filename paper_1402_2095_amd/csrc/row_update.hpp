@@ -100,21 +100,6 @@ __device__ __forceinline__ StepInfo step_info(const StepArgs<Real>& a, int k) {
     return s;
 }
 
-// Selected pairs: sum_r q_i^r q_j^r from q_n into the pair accumulators.
-template <typename Real, int RPT>
-__device__ __forceinline__ void pair_update(const StepArgs<Real>& a, const StepInfo& si, const Real* qr, int64_t pk) {
-    using V = Vec<Real, RPT>;
-    const int64_t R = a.R;
-    const int64_t pi = a.pairs[2 * pk], pj = a.pairs[2 * pk + 1];
-    const V qi = load_vec<Real, RPT>(qr + pi * R + si.r0);
-    const V qj = load_vec<Real, RPT>(qr + pj * R + si.r0);
-    double x = 0.0;
-#pragma unroll
-    for (int m = 0; m < RPT; ++m) x += double(qi.v[m]) * double(qj.v[m]);
-    x = group_sum(x, si.tpr);
-    if (si.rq == 0 && si.acc_on) acc_update(a.pblk, a.ps1, a.ps2, pk, x, si.close);
-}
-
 // (p, s) of row i: rows are grouped by 2^lg, and inside a group each component
 // is a contiguous [2^lg][R] block, so one component of a group spans at least
 // a 128-byte line whatever R is.  Returns the row's component-0 slice;
@@ -125,6 +110,41 @@ __device__ __forceinline__ Real* ps_row(Real* ps, int64_t i, int D, int64_t R, i
 }
 __device__ __forceinline__ int64_t ps_stride(int64_t R, int lg) { return R << lg; }
 
+// (p, s) at step n is in buffer n & 1; step n writes step n+1's into the other.
+template <typename Real>
+__device__ __forceinline__ Real* ps_at_step(const StepArgs<Real>& a, int64_t n) {
+    return (n & 1) ? a.ps_b : a.ps;
+}
+
+// FP64 sum over the thread's replicas of x_m y_m, then over the row's lanes.
+template <typename Real, int RPT>
+__device__ __forceinline__ double dot_row(const Vec<Real, RPT>& x, const Vec<Real, RPT>& y, int tpr) {
+    double s = 0.0;
+#pragma unroll
+    for (int m = 0; m < RPT; ++m) s += double(x.v[m]) * double(y.v[m]);
+    return group_sum(s, tpr);
+}
+
+// Selected pairs: sum_r q_i^r q_j^r from q_n (and sum_r p_i^r p_j^r from p_n
+// when p-p accumulators are kept) into the pair accumulators.
+template <typename Real, int RPT>
+__device__ __forceinline__ void pair_update(const StepArgs<Real>& a, const StepInfo& si, const Real* qr, int64_t pk) {
+    using V = Vec<Real, RPT>;
+    const int64_t R = a.R;
+    const int64_t pi = a.pairs[2 * pk], pj = a.pairs[2 * pk + 1];
+    const V qi = load_vec<Real, RPT>(qr + pi * R + si.r0);
+    const V qj = load_vec<Real, RPT>(qr + pj * R + si.r0);
+    const double x = dot_row<Real, RPT>(qi, qj, si.tpr);
+    if (si.rq == 0 && si.acc_on) acc_update(a.pblk, a.ps1, a.ps2, pk, x, si.close);
+    if (a.pp_blk != nullptr) {
+        const Real* psr = ps_at_step(a, si.n);
+        const V p_i = load_vec<Real, RPT>(ps_row(psr, pi, a.D(), R, a.ps_lg) + si.r0);
+        const V p_j = load_vec<Real, RPT>(ps_row(psr, pj, a.D(), R, a.ps_lg) + si.r0);
+        const double y = dot_row<Real, RPT>(p_i, p_j, si.tpr);
+        if (si.rq == 0 && si.acc_on) acc_update(a.pp_blk, a.pp_s1, a.pp_s2, pk, y, si.close);
+    }
+}
+
 // The thread's slice of one row's state.
 template <typename Real, int NS, int RPT>
 struct RowState {
@@ -133,13 +153,14 @@ struct RowState {
 };
 
 template <typename Real, int NS, int RPT, bool NT>
-__device__ __forceinline__ RowState<Real, NS, RPT> load_row(const StepArgs<Real>& a, const Real* qr, int64_t i,
-                                                            int r0) {
+__device__ __forceinline__ RowState<Real, NS, RPT> load_row(const StepArgs<Real>& a, const StepInfo& si,
+                                                            const Real* qr, int64_t i) {
     RowState<Real, NS, RPT> st;
     const int64_t R = a.R;
+    const int r0 = si.r0;
     constexpr int D = NS + 1;
     st.q = load_vec<Real, RPT>(qr + i * R + r0);
-    const Real* psrow = ps_row(a.ps, i, D, R, a.ps_lg) + r0;
+    const Real* psrow = ps_row(ps_at_step(a, si.n), i, D, R, a.ps_lg) + r0;
     const int64_t cs = ps_stride(R, a.ps_lg);
     st.p = load_state<Real, RPT, NT>(psrow);
 #pragma unroll
@@ -200,15 +221,16 @@ __device__ __forceinline__ Vec<Real, RPT> finish_row(const StepArgs<Real>& a, co
     constexpr int D = NS + 1;
     const int64_t R = a.R;
     if (a.dblk != nullptr) {
-        double x = 0.0;
-#pragma unroll
-        for (int m = 0; m < RPT; ++m) x += double(st.q.v[m]) * double(st.q.v[m]);
-        x = group_sum(x, si.tpr);
+        const double x = dot_row<Real, RPT>(st.q, st.q, si.tpr);
         if (si.rq == 0 && si.acc_on) acc_update(a.dblk, a.ds1, a.ds2, i, x, si.close);
+    }
+    if (a.dp_blk != nullptr) {
+        const double y = dot_row<Real, RPT>(st.p, st.p, si.tpr);
+        if (si.rq == 0 && si.acc_on) acc_update(a.dp_blk, a.dp_s1, a.dp_s2, i, y, si.close);
     }
     RowState<Real, NS, RPT> nx;
     const bool ok = ou_update<Real, NS, RPT>(a.TS, a.TS + D * D, a.h, a.hh, st, acc, xi, nx);
-    Real* psrow = ps_row(a.ps, i, D, R, a.ps_lg) + si.r0;
+    Real* psrow = ps_row(ps_at_step(a, si.n + 1), i, D, R, a.ps_lg) + si.r0;
     const int64_t cs = ps_stride(R, a.ps_lg);
     store_state<Real, RPT, NT>(psrow, nx.p);
 #pragma unroll

@@ -6,6 +6,8 @@
 //     row slice of p and s in registers for the whole launch;
 //   - the block sums of the accumulators live in LDS; s1 / s2 in global
 //     memory are touched only when a block closes;
+//   - with p-p pair accumulators, p_n is mirrored to two more LDS buffers so
+//     the pairs can read it while rows write p_{n+1};
 //   - one workgroup barrier per step separates reading q_n from writing
 //     q_{n+1}, which go to alternating LDS buffers.
 // The arithmetic of a step is the same as in the sparse and dense kernels
@@ -32,29 +34,39 @@ __global__ __launch_bounds__(1024) void small_dense_kernel(const StepArgs<Real> 
     const int64_t i = tid >> a.lg_tpr;
     const bool active = i < N;
     const int64_t nd = a.dblk != nullptr ? N : 0;
-    // LDS layout: block sums (FP64) | q[2][N][R] | M[N][N] (if in LDS)
+    const bool kp = a.pp_blk != nullptr;          // p-p accumulators kept
+    const int64_t np = a.npairs, nacc = np + nd;  // per kind (q, then p)
+    const bool pp_pairs = kp && np > 0;
+    // LDS layout: block sums (FP64) [q pairs | q diag | p pairs | p diag] | q[2][N][R]
+    //             | p[2][N][R] (p-p pairs only) | M[N][N] (if in LDS)
     double* bl = smem_d;
-    Real* qb = reinterpret_cast<Real*>(bl + a.npairs + nd);
+    Real* qb = reinterpret_cast<Real*>(bl + (kp ? 2 : 1) * nacc);
+    Real* pb = qb + 2 * N * R;
     const Real* Mx = a.mdense;
     if (a.m_in_lds) {
-        Real* Ml = qb + 2 * N * R;
+        Real* Ml = pb + (pp_pairs ? 2 * N * R : 0);
         for (int64_t x = tid; x < N * N; x += nthr) Ml[x] = a.mdense[x];
         Mx = Ml;
     }
     const int64_t n0 = a.step_base[0];
     const Real* qg = (n0 & 1) ? a.q1 : a.q0;
     for (int64_t x = tid; x < N * R; x += nthr) qb[(n0 & 1) * N * R + x] = qg[x];
-    for (int64_t x = tid; x < a.npairs; x += nthr) bl[x] = a.pblk[x];
-    for (int64_t x = tid; x < nd; x += nthr) bl[a.npairs + x] = a.dblk[x];
+    for (int64_t x = tid; x < np; x += nthr) bl[x] = a.pblk[x];
+    for (int64_t x = tid; x < nd; x += nthr) bl[np + x] = a.dblk[x];
+    if (kp) {
+        for (int64_t x = tid; x < np; x += nthr) bl[nacc + x] = a.pp_blk[x];
+        for (int64_t x = tid; x < nd; x += nthr) bl[nacc + np + x] = a.dp_blk[x];
+    }
 
     RowState<Real, NS, RPT> st;
     if (active) {
         st.q = load_vec<Real, RPT>(qg + i * R + r0);
-        const Real* psrow = ps_row(a.ps, i, D, R, a.ps_lg) + r0;
+        const Real* psrow = ps_row(ps_at_step(a, n0), i, D, R, a.ps_lg) + r0;
         const int64_t cs = ps_stride(R, a.ps_lg);
         st.p = load_vec<Real, RPT>(psrow);
 #pragma unroll
         for (int c = 0; c < NS; ++c) st.s[c] = load_vec<Real, RPT>(psrow + (c + 1) * cs);
+        if (pp_pairs) store_vec<Real, RPT>(pb + (n0 & 1) * N * R + i * R + r0, st.p);
     }
     const Real* T = a.TS;
     const Real* S = a.TS + D * D;
@@ -67,18 +79,28 @@ __global__ __launch_bounds__(1024) void small_dense_kernel(const StepArgs<Real> 
         const bool close = acc_on && ((n - a.burn_in + 1) % a.block_len) == 0;
         const Real* qr = qb + (n & 1) * N * R;
         Real* qw = qb + ((n + 1) & 1) * N * R;
+        // one block-sum update of accumulator slot x in LDS
+        auto fold = [&](double* blk, double* s1, double* s2, int64_t idx, int64_t slot, double v) {
+            const double b = blk[slot] + v;
+            if (close) {
+                s1[idx] = s1[idx] + b;
+                s2[idx] = s2[idx] + b * b;
+                blk[slot] = 0.0;
+            } else {
+                blk[slot] = b;
+            }
+        };
         if (acc_on) {
-            for (int64_t pk = tid; pk < a.npairs; pk += nthr) {
-                const int64_t pa = a.pairs[2 * pk], pb = a.pairs[2 * pk + 1];
+            for (int64_t pk = tid; pk < np; pk += nthr) {
+                const int64_t ia = a.pairs[2 * pk], ib = a.pairs[2 * pk + 1];
                 double x = 0.0;
-                for (int64_t r = 0; r < R; ++r) x += double(qr[pa * R + r]) * double(qr[pb * R + r]);
-                const double b = bl[pk] + x;
-                if (close) {
-                    a.ps1[pk] = a.ps1[pk] + b;
-                    a.ps2[pk] = a.ps2[pk] + b * b;
-                    bl[pk] = 0.0;
-                } else {
-                    bl[pk] = b;
+                for (int64_t r = 0; r < R; ++r) x += double(qr[ia * R + r]) * double(qr[ib * R + r]);
+                fold(bl, a.ps1, a.ps2, pk, pk, x);
+                if (pp_pairs) {
+                    const Real* pr = pb + (n & 1) * N * R;
+                    double y = 0.0;
+                    for (int64_t r = 0; r < R; ++r) y += double(pr[ia * R + r]) * double(pr[ib * R + r]);
+                    fold(bl, a.pp_s1, a.pp_s2, pk, nacc + pk, y);
                 }
             }
         }
@@ -93,19 +115,11 @@ __global__ __launch_bounds__(1024) void small_dense_kernel(const StepArgs<Real> 
                 for (int m = 0; m < RPT; ++m) acc[m] = fmaR(mij, qj.v[m], acc[m]);
             }
             if (nd) {
-                double x = 0.0;
-#pragma unroll
-                for (int m = 0; m < RPT; ++m) x += double(st.q.v[m]) * double(st.q.v[m]);
-                x = group_sum(x, tpr);
-                if (rq == 0 && acc_on) {
-                    const double b = bl[a.npairs + i] + x;
-                    if (close) {
-                        a.ds1[i] = a.ds1[i] + b;
-                        a.ds2[i] = a.ds2[i] + b * b;
-                        bl[a.npairs + i] = 0.0;
-                    } else {
-                        bl[a.npairs + i] = b;
-                    }
+                const double x = dot_row<Real, RPT>(st.q, st.q, tpr);
+                if (rq == 0 && acc_on) fold(bl, a.ds1, a.ds2, i, np + i, x);
+                if (kp) {
+                    const double y = dot_row<Real, RPT>(st.p, st.p, tpr);
+                    if (rq == 0 && acc_on) fold(bl, a.dp_s1, a.dp_s2, i, nacc + np + i, y);
                 }
             }
             Real xi[NS + 1][RPT];
@@ -116,6 +130,7 @@ __global__ __launch_bounds__(1024) void small_dense_kernel(const StepArgs<Real> 
             RowState<Real, NS, RPT> nx;
             ok = ou_update<Real, NS, RPT>(T, S, a.h, a.hh, st, acc, xi, nx) && ok;
             store_vec<Real, RPT>(qw + i * R + r0, nx.q);
+            if (pp_pairs) store_vec<Real, RPT>(pb + ((n + 1) & 1) * N * R + i * R + r0, nx.p);
             st = nx;
         }
         __syncthreads();
@@ -124,14 +139,18 @@ __global__ __launch_bounds__(1024) void small_dense_kernel(const StepArgs<Real> 
     Real* qgo = (nend & 1) ? a.q1 : a.q0;
     if (active) {
         store_vec<Real, RPT>(qgo + i * R + r0, st.q);
-        Real* psrow = ps_row(a.ps, i, D, R, a.ps_lg) + r0;
+        Real* psrow = ps_row(ps_at_step(a, nend), i, D, R, a.ps_lg) + r0;
         const int64_t cs = ps_stride(R, a.ps_lg);
         store_vec<Real, RPT>(psrow, st.p);
 #pragma unroll
         for (int c = 0; c < NS; ++c) store_vec<Real, RPT>(psrow + (c + 1) * cs, st.s[c]);
     }
-    for (int64_t x = tid; x < a.npairs; x += nthr) a.pblk[x] = bl[x];
-    for (int64_t x = tid; x < nd; x += nthr) a.dblk[x] = bl[a.npairs + x];
+    for (int64_t x = tid; x < np; x += nthr) a.pblk[x] = bl[x];
+    for (int64_t x = tid; x < nd; x += nthr) a.dblk[x] = bl[np + x];
+    if (kp) {
+        for (int64_t x = tid; x < np; x += nthr) a.pp_blk[x] = bl[nacc + x];
+        for (int64_t x = tid; x < nd; x += nthr) a.dp_blk[x] = bl[nacc + np + x];
+    }
     if (!ok) atomicOr(a.flag, 1);
     __syncthreads();
     if (tid == 0) const_cast<int64_t*>(a.step_base)[0] = nend;

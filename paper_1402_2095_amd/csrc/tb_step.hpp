@@ -10,13 +10,13 @@
 //   - p, s and the CSR row live in registers for the whole launch;
 //   - the diagonal block sum of an output row lives in a register; s1 / s2
 //     are updated in global memory only when a block closes;
-//   - q of output rows that appear in a selected pair is copied each step to
-//     a snapshot buffer; a second small kernel then forms the pair products
-//     step by step, in the same order as the one-step kernel.
-// Global state is double-buffered across launches so no workgroup can read a
-// halo row that another workgroup of the same launch has already written
-// back: q is read from buffer n0 & 1 and written to (n0 + KT) & 1 (KT odd),
-// (p, s) is read from ps_in and written to ps_out.
+//   - q (and p, with p-p accumulators) of output rows that appear in a
+//     selected pair is copied each step to a snapshot buffer; a second small
+//     kernel then forms the pair products step by step, in the same order as
+//     the one-step kernel.
+// Global state is double-buffered, so no workgroup can read a halo row that
+// another workgroup of the same launch has already written back: q and
+// (p, s) are read from buffer n0 & 1 and written to (n0 + KT) & 1 (KT odd).
 // The arithmetic of each row and step is exactly the one-step kernel's
 // (same gather order, noise, update), so trajectories are bit-identical.
 #pragma once
@@ -55,11 +55,11 @@ __global__ __launch_bounds__(tb_max_block(sizeof(Real) == 8, NS)) void tb_step_k
     int dcol[G];
     Real dval[G];
     int nz = 0;
-    double blk = 0.0;
+    double blk = 0.0, blkp = 0.0;
     int32_t pslot = -1;
     if (row_ok) {
         st.q = load_vec<Real, RPT>(qg + i * R + r0);
-        const Real* psrow = ps_row(tb.ps_in, i, D, R, a.ps_lg) + r0;
+        const Real* psrow = ps_row(ps_at_step(a, n0), i, D, R, a.ps_lg) + r0;
         const int64_t cs = ps_stride(R, a.ps_lg);
         st.p = load_vec<Real, RPT>(psrow);
 #pragma unroll
@@ -73,6 +73,7 @@ __global__ __launch_bounds__(tb_max_block(sizeof(Real) == 8, NS)) void tb_step_k
         }
         store_vec<Real, RPT>(qlds + int64_t(e) * R + r0, st.q);
         if (output && a.dblk != nullptr && rq == 0) blk = a.dblk[i];
+        if (output && a.dp_blk != nullptr && rq == 0) blkp = a.dp_blk[i];
         if (output && tb.pair_slot != nullptr) pslot = tb.pair_slot[i];
     }
     const Real* T_ = a.TS;
@@ -89,10 +90,7 @@ __global__ __launch_bounds__(tb_max_block(sizeof(Real) == 8, NS)) void tb_step_k
         Real* nxt = qlds + int64_t((s + 1) & 1) * E * R;
         if (output) {
             if (a.dblk != nullptr) {
-                double x = 0.0;
-#pragma unroll
-                for (int m = 0; m < RPT; ++m) x += double(st.q.v[m]) * double(st.q.v[m]);
-                x = group_sum(x, tpr);
+                const double x = dot_row<Real, RPT>(st.q, st.q, tpr);
                 if (rq == 0 && acc_on) {
                     blk = blk + x;
                     if (close) {
@@ -102,7 +100,22 @@ __global__ __launch_bounds__(tb_max_block(sizeof(Real) == 8, NS)) void tb_step_k
                     }
                 }
             }
-            if (pslot >= 0) store_vec<Real, RPT>(tb.snap + (int64_t(s) * tb.nslots + pslot) * R + r0, st.q);
+            if (a.dp_blk != nullptr) {
+                const double y = dot_row<Real, RPT>(st.p, st.p, tpr);
+                if (rq == 0 && acc_on) {
+                    blkp = blkp + y;
+                    if (close) {
+                        a.dp_s1[i] = a.dp_s1[i] + blkp;
+                        a.dp_s2[i] = a.dp_s2[i] + blkp * blkp;
+                        blkp = 0.0;
+                    }
+                }
+            }
+            if (pslot >= 0) {
+                store_vec<Real, RPT>(tb.snap + (int64_t(2 * s) * tb.nslots + pslot) * R + r0, st.q);
+                if (a.pp_blk != nullptr)
+                    store_vec<Real, RPT>(tb.snap + (int64_t(2 * s + 1) * tb.nslots + pslot) * R + r0, st.p);
+            }
         }
         // rows still needed after this step: e in [(s+1) w, E - (s+1) w)
         if (row_ok && e >= (s + 1) * w && e < E - (s + 1) * w) {
@@ -130,12 +143,13 @@ __global__ __launch_bounds__(tb_max_block(sizeof(Real) == 8, NS)) void tb_step_k
     }
     if (output) {
         store_state<Real, RPT, true>(qgo + i * R + r0, st.q);
-        Real* psrow = ps_row(tb.ps_out, i, D, R, a.ps_lg) + r0;
+        Real* psrow = ps_row(ps_at_step(a, n0 + KT), i, D, R, a.ps_lg) + r0;
         const int64_t cs = ps_stride(R, a.ps_lg);
         store_state<Real, RPT, true>(psrow, st.p);
 #pragma unroll
         for (int c = 0; c < NS; ++c) store_state<Real, RPT, true>(psrow + (c + 1) * cs, st.s[c]);
         if (a.dblk != nullptr && rq == 0) a.dblk[i] = blk;
+        if (a.dp_blk != nullptr && rq == 0) a.dp_blk[i] = blkp;
         if (!ok) atomicOr(a.flag, 1);
     }
 }
@@ -154,13 +168,15 @@ __global__ __launch_bounds__(256) void tb_pairs_kernel(const StepArgs<Real> a, c
         const int64_t n = n0 + s;
         const bool acc_on = n >= a.burn_in;
         const bool close = acc_on && ((n - a.burn_in + 1) % a.block_len) == 0;
-        const Vec<Real, RPT> qi = load_vec<Real, RPT>(tb.snap + (int64_t(s) * tb.nslots + si) * R + r0);
-        const Vec<Real, RPT> qj = load_vec<Real, RPT>(tb.snap + (int64_t(s) * tb.nslots + sj) * R + r0);
-        double x = 0.0;
-#pragma unroll
-        for (int m = 0; m < RPT; ++m) x += double(qi.v[m]) * double(qj.v[m]);
-        x = group_sum(x, tpr);
+        const Real* sq = tb.snap + int64_t(2 * s) * tb.nslots * R + r0;
+        const double x = dot_row<Real, RPT>(load_vec<Real, RPT>(sq + si * R), load_vec<Real, RPT>(sq + sj * R), tpr);
         if (rq == 0 && acc_on) acc_update(a.pblk, a.ps1, a.ps2, pk, x, close);
+        if (a.pp_blk != nullptr) {
+            const Real* sp = tb.snap + int64_t(2 * s + 1) * tb.nslots * R + r0;
+            const double y =
+                dot_row<Real, RPT>(load_vec<Real, RPT>(sp + si * R), load_vec<Real, RPT>(sp + sj * R), tpr);
+            if (rq == 0 && acc_on) acc_update(a.pp_blk, a.pp_s1, a.pp_s2, pk, y, close);
+        }
     }
 }
 

@@ -1,0 +1,141 @@
+"""GPU parity of the momentum form of the estimator (Eq. 7: <p_i p_j>, p_n
+sampled with q_n), kept beside the position form with acc_pp.
+
+Every step form is covered: the one-step sparse kernel (plain CSR and the
+coded form), the dense epilogue (FP64 and split-BF16x3), the persistent
+small-system kernel and the temporally blocked kernel.  Accumulators of both
+blocks are compared with the FP64 oracle (same tolerances as the position
+form: 1e-10 FP64, 1e-4 FP32 normwise over 1000 steps); the blocked kernel is
+compared bit for bit with the one-step kernel; statistics are checked
+against the exact momentum response of the integrated step.
+"""
+import numpy as np
+import pytest
+
+import fth_inputs as fi
+import oracle
+from oracle import exact
+from paper_1402_2095_amd import fth
+
+pytestmark = pytest.mark.gpu
+
+TOL = {fth.FTH_FP64: 1e-10, fth.FTH_FP32: 1e-4, fth.FTH_FP32_BF16X3: 1e-4}
+
+
+def normwise(a, b):
+    den = np.max(np.abs(b))
+    return float(np.max(np.abs(a - b)) / den) if den > 0 else float(np.max(np.abs(a)))
+
+
+def run_parity(M, h, g, R, prec, pairs, label, expect_kernel, steps=(1, 10, 100, 1000)):
+    n = M.shape[0] if isinstance(M, np.ndarray) else M.n
+    sol = fth.Solver(M, g.A_p, g.C_p, h, pairs=pairs, replicas=R, precision=prec, seed=77, stream_id=4,
+                     burn_in=3, block_len=9, acc_diag=True, acc_pp=True, steps_per_graph=16, temporal_steps=-1)
+    Mo = M.astype(np.float64) if isinstance(M, np.ndarray) else M
+    orc = oracle.OracleRun(Mo, g.A_p, g.C_p, h, R, np.concatenate([pairs, fi.diag_pairs(n)]), seed=77, stream=4,
+                           burn_in=3, block_len=9, pp=True)
+    assert fth.fth_num_outputs(sol.ctx) == 2 * (len(pairs) + n)
+    done = 0
+    for target in steps:
+        sol.run(target - done)
+        orc.run(target - done)
+        done = target
+        blk, s1, s2, nb, step = sol.accumulators()
+        A = len(pairs) + n
+        errs = {"acc_q": normwise((s1 + blk)[:A], (orc.s1 + orc.blk)[:A]),
+                "acc_p": normwise((s1 + blk)[A:], (orc.s1 + orc.blk)[A:])}
+        if nb:
+            errs["s2_p"] = normwise(s2[A:], orc.s2[A:])
+        print(f"  [{label}] step {done}: " + " ".join(f"{k}={v:.2e}" for k, v in errs.items()), flush=True)
+        for k, v in errs.items():
+            assert v <= TOL[prec], (label, done, k, v)
+    print(f"  [{label}] {sol.kernel_name}", flush=True)
+    assert expect_kernel in sol.kernel_name
+    est, se, _ = sol.read()
+    m_o, _ = orc.estimates()
+    assert normwise(est, m_o) <= 10 * TOL[prec]
+    sol.close()
+
+
+@pytest.mark.parametrize("R,prec,coded", [(8, fth.FTH_FP64, True), (8, fth.FTH_FP32, True), (2, fth.FTH_FP32, False),
+                                          (32, fth.FTH_FP32, False)])
+def test_sparse_momentum_parity(R, prec, coded):
+    M = fi.laplacian3d_csr(8, 0.1, dtype=np.float64) if coded else fi.banded_spd_csr(1001, 4004, dtype=np.float64)
+    lam = fi.laplacian3d_lambda_max(8, 0.1) if coded else fi.gershgorin_max(M)
+    g = fi.load_gle("invsqrt_ns4")
+    run_parity(M, fi.dt_rule(lam), g, R, prec, fi.random_pairs(M.n, 48, 12), f"csr R={R}",
+               "CODED=1" if coded else "csr_step_kernel")
+
+
+@pytest.mark.parametrize("prec", [fth.FTH_FP64, fth.FTH_FP32_BF16X3], ids=["fp64", "bf16x3"])
+def test_dense_momentum_parity(prec):
+    M = fi.dense_ggt(520, 31)
+    h = fi.dt_rule(fi.power_lambda_max(M.astype(np.float64)))
+    run_parity(M, h, fi.load_gle("invsqrt_ns4"), 32, prec, fi.random_pairs(520, 40, 13), "dense",
+               "dense_epilogue_kernel")
+
+
+@pytest.mark.parametrize("R,prec", [(4, fth.FTH_FP64), (8, fth.FTH_FP32)])
+def test_small_momentum_parity(R, prec):
+    M, lam = fi.haar_spd(60, 71, 1.0, 100.0)
+    g = fi.load_gle("invsqrt_ns4")
+    g = fi.GLE(4, g.A_p * 3.0, g.C_p * 3.0)  # alpha = gamma = 3: window moves to lambda in [0.9, 109]
+    run_parity(M, fi.dt_rule(lam.max()), g, R, prec, fi.random_pairs(60, 20, 14), "small", "small_dense_kernel",
+               steps=(1, 10, 100, 1000, 3000))
+
+
+@pytest.mark.parametrize("kt", [3, 5])
+def test_blocked_momentum_bit_identical(kt):
+    M = fi.banded_spd_csr(20011, 17)
+    h = fi.dt_rule(fi.gershgorin_max(M))
+    g = fi.load_gle("fermi_b20_ns4")
+    kw = dict(pairs=fi.random_pairs(M.n, 64, 15), replicas=32, seed=8, acc_diag=True, acc_pp=True, burn_in=2,
+              block_len=4, steps_per_graph=10)
+    a = fth.Solver(M, g.A_p, g.C_p, h, temporal_steps=kt, **kw).run(1).run(44)
+    b = fth.Solver(M, g.A_p, g.C_p, h, temporal_steps=-1, **kw).run(1).run(44)
+    assert "tb_step_kernel" in a.kernel_name
+    for x, y in zip(a.state(), b.state()):
+        assert np.array_equal(x, y)
+    for x, y in zip(a.accumulators()[:3], b.accumulators()[:3]):
+        assert np.array_equal(x, y)
+
+
+def test_momentum_estimates_match_exact_response():
+    """<p_i p_j> from the GPU against U gh_p(Lambda) U^T on the periodic 12^3
+    Laplacian (the FFT diagonalises it), and the white-noise closed form
+    kT (I - h^2 M / 4)^-1 on a banded matrix."""
+    n_side = 12
+    M = fi.laplacian3d_csr(n_side, 0.1)
+    g = fi.load_gle("invsqrt_ns4")
+    h = fi.dt_rule(fi.laplacian3d_lambda_max(n_side, 0.1))
+    pairs = fi.random_pairs(M.n, 256, 16)
+    sol = fth.Solver(M, g.A_p, g.C_p, h, pairs=pairs, replicas=32, seed=19, burn_in=2000, block_len=1000,
+                     acc_diag=True, acc_pp=True)
+    sol.run(40000)
+    est, se, _ = sol.read()
+    T, S = oracle.propagator(g.A_p, g.C_p, h)
+    C = exact.laplacian_function(n_side, 0.1, lambda lam: exact.gh_p(lam, g.A_p, g.C_p, h, T, S))
+    allp = np.concatenate([pairs, fi.diag_pairs(M.n)])
+    ref = exact.laplacian_element(C, allp[:, 0], allp[:, 1])
+    A = len(allp)
+    z = (est[A:] - ref) / se[A:]
+    print(f"[pp stats] max|z| {np.max(np.abs(z)):.2f}, mean z {np.mean(z):.3f}", flush=True)
+    assert np.max(np.abs(z)) < 5.5
+
+    Mb = fi.banded_spd_csr(300, 5, dtype=np.float64)
+    hb = 0.9 / np.sqrt(fi.gershgorin_max(Mb))
+    kT = 1.0
+    w = fi.white_noise_gle(1.0, kT)
+    sol = fth.Solver(Mb, w.A_p, w.C_p, hb, replicas=64, precision=fth.FTH_FP64, seed=20, burn_in=500,
+                     block_len=500, acc_diag=True, acc_pp=True)
+    sol.run(30000)
+    est, se, _ = sol.read()
+    dense = np.zeros((300, 300))
+    for i in range(300):
+        for k in range(Mb.row_ptr[i], Mb.row_ptr[i + 1]):
+            dense[i, Mb.col[k]] = Mb.val[k]
+    ref = np.diag(kT * np.linalg.inv(np.eye(300) - hb * hb * dense / 4))
+    z = (est[300:] - ref) / se[300:]
+    print(f"[pp white] max|z| {np.max(np.abs(z)):.2f}", flush=True)
+    assert np.max(np.abs(z)) < 5.5
+    assert np.max(np.abs((est[300:] - kT) / se[300:])) > 6.0

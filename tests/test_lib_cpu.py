@@ -107,7 +107,8 @@ def test_footprint_accounting():
     csr = fi.laplacian3d_csr(8)
     b = fth.fth_footprint_bytes(csr, 4, 8, 10, True, fth.FTH_FP32)
     n, nnz = csr.n, csr.nnz
-    expect = (n + 1) * 8 + nnz * 8 + n * 8 * 4 * 7 + (10 + n) * 24 + 10 * 8 + 2 * 25 * 4 + 64
+    # q and (p, s) are both double-buffered: 2 + 2 (ns + 1) vectors of R reals per row
+    expect = (n + 1) * 8 + nnz * 8 + n * 8 * 4 * 12 + (10 + n) * 24 + 10 * 8 + 2 * 25 * 4 + 64
     assert b == expect
     # the paper's count: M + (3 + S) N + 2 A reals; state bytes dominate and scale with R
-    assert fth.fth_footprint_bytes(csr, 4, 16, 10, True, fth.FTH_FP32) - b == n * 8 * 4 * 7
+    assert fth.fth_footprint_bytes(csr, 4, 16, 10, True, fth.FTH_FP32) - b == n * 8 * 4 * 12
