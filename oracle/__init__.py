@@ -161,10 +161,12 @@ class OracleRun:
     ``pairs`` is int32 [A, 2]; diagonal entries are pairs (i, i).  With
     ``pp=True`` every pair is accumulated twice: first as <q_i q_j>, then (in
     a second block of the same order) as the momentum form <p_i p_j> of Eq. 7.
+    With ``traces=True`` three trace estimators follow (Sec. I): sum_i
+    <q_i^2>, <q^T M q> and, with pp, sum_i <p_i^2>.
     """
 
     def __init__(self, M, A_p, C_p, h, R, pairs, seed=0, stream=0, burn_in=0,
-                 block_len=100, T=None, S=None, nthreads=0, pp=False):
+                 block_len=100, T=None, S=None, nthreads=0, pp=False, traces=False):
         if isinstance(M, np.ndarray):
             self.fmt = 0
             self.N = M.shape[0]
@@ -196,9 +198,14 @@ class OracleRun:
         self.p = np.zeros((N, R))
         self.s = np.zeros((ns, N, R))
         base = np.asarray(pairs, dtype=np.int32).reshape(-1, 2)
-        self.pairs = np.ascontiguousarray(np.concatenate([base, base]) if pp else base)
-        self.kinds = np.ascontiguousarray(np.repeat(np.array([0, 1], dtype=np.int32) if pp else np.zeros(1, np.int32),
-                                                    len(base)))
+        kinds = np.repeat(np.array([0, 1] if pp else [0], dtype=np.int32), len(base))
+        allp = np.concatenate([base, base]) if pp else base
+        if traces:
+            tk = np.array([2, 3, 4] if pp else [2, 3], dtype=np.int32)
+            kinds = np.concatenate([kinds, tk])
+            allp = np.concatenate([allp, np.zeros((len(tk), 2), dtype=np.int32)])
+        self.pairs = np.ascontiguousarray(allp, dtype=np.int32)
+        self.kinds = np.ascontiguousarray(kinds, dtype=np.int32)
         A = len(self.pairs)
         self.blk = np.zeros(A)
         self.s1 = np.zeros(A)

@@ -125,10 +125,15 @@ void orc_philox_batch(int64_t count, const uint32_t* ctr, const uint32_t* key, u
  *   blk  = sum of x over the current (incomplete) block,
  *   s1   = sum over completed blocks of the block sums,
  *   s2   = sum over completed blocks of the squared block sums,
- * where x(n) = sum_r q_i^r(n) q_j^r(n) for every n >= burn_in, or, for a pair
- * with kinds[k] == 1, the momentum form sum_r p_i^r(n) p_j^r(n) of Eq. 7
- * (p_n, the momentum at the start of step n, the same instant as q_n); kinds
- * may be NULL (all position pairs).  A block closes after the step with
+ * where x(n) = sum_r q_i^r(n) q_j^r(n) for every n >= burn_in, or, by kinds[k]:
+ *   1: the momentum form sum_r p_i^r(n) p_j^r(n) of Eq. 7 (p_n, the momentum
+ *      at the start of step n, the same instant as q_n);
+ *   2: the trace sum_i sum_r q_i^r(n)^2 (Tr of the position response);
+ *   3: sum_i sum_r q_i^r(n) (M q(n))_i^r, i.e. q^T M q = -q . F, the trace
+ *      Tr[O g(M)] with O = M (Sec. I, traces of the form Tr O f(M));
+ *   4: the kinetic trace sum_i sum_r p_i^r(n)^2 (Tr f(M) of Sec. I);
+ * the pair indices of kinds 2-4 are ignored.  kinds may be NULL (all
+ * position pairs).  A block closes after the step with
  * (n - burn_in + 1) % L == 0 and then *nblocks grows by one.
  *
  * One step n (all dofs and replicas):
@@ -183,11 +188,17 @@ int orc_run(int64_t N, int fmt, const double* dense, const int64_t* row_ptr,
             const int close = ((n - burn_in + 1) % L) == 0;
             #pragma omp parallel for schedule(static) if(npairs * R >= 16384)
             for (int64_t k = 0; k < npairs; ++k) {
-                const int64_t a = pairs[2 * k], b = pairs[2 * k + 1];
-                const double* v = (kinds && kinds[k] == 1) ? p : q;
+                const int kind = kinds ? kinds[k] : 0;
                 double x = 0.0;
-                for (int64_t r = 0; r < R; ++r)
-                    x += v[a * R + r] * v[b * R + r];
+                if (kind <= 1) {
+                    const int64_t a = pairs[2 * k], b = pairs[2 * k + 1];
+                    const double* v = kind == 1 ? p : q;
+                    for (int64_t r = 0; r < R; ++r)
+                        x += v[a * R + r] * v[b * R + r];
+                } else {
+                    for (int64_t i = 0; i < N * R; ++i)
+                        x += kind == 2 ? q[i] * q[i] : kind == 3 ? -q[i] * F[i] : p[i] * p[i];
+                }
                 blk[k] += x;
                 if (close) {
                     s1[k] += blk[k];

@@ -246,3 +246,38 @@ def test_momentum_form_fitted_gle_matches_exact(orc):
     ref = exact.gh_p_matrix(M, g.A_p, g.C_p, h)[pairs[:, 0], pairs[:, 1]]
     z = (mean[A:] - ref) / se[A:]
     assert np.max(np.abs(z)) < 4.5, z
+
+
+def test_trace_estimators(orc):
+    """Traces of Sec. I: sum_i <q_i^2> = Tr g_h(M), <q^T M q> = Tr[M g_h(M)]
+    (= -<q . F>) and sum_i <p_i^2> = Tr gh_p(M), from the eigenvalues; with
+    white noise <q^T M q> = kT Tr (I - h^2 M / 4)^-1 in closed form.  The
+    trace of the positions also equals the sum of the diagonal estimates of
+    the same run up to rounding (every row is in the trace)."""
+    N, R = 7, 64
+    M, lam = random_spd(N, 44, 0.3, 8.0)
+    g = fth_inputs.load_gle("invsqrt_ns4")
+    h = 0.1 / np.sqrt(lam.max())
+    diag = fth_inputs.diag_pairs(N)
+    run = oracle.OracleRun(M, g.A_p, g.C_p, h, R, diag, seed=37, burn_in=2000, block_len=400, pp=True,
+                           traces=True)
+    run.run(14000)
+    mean, se = run.estimates()
+    tr_q, tr_qmq, tr_p = mean[2 * N:]
+    assert abs(tr_q - mean[:N].sum()) <= 1e-12 * abs(tr_q)
+    assert abs(tr_p - mean[N:2 * N].sum()) <= 1e-12 * abs(tr_p)
+    T, S = oracle.propagator(g.A_p, g.C_p, h)
+    ref = np.array([exact.gh(lam, g.A_p, g.C_p, h, T, S).sum(),
+                    (lam * exact.gh(lam, g.A_p, g.C_p, h, T, S)).sum(),
+                    exact.gh_p(lam, g.A_p, g.C_p, h, T, S).sum()])
+    z = (mean[2 * N:] - ref) / se[2 * N:]
+    assert np.max(np.abs(z)) < 4.5, z
+
+    kT = 0.8
+    hw = 0.9 / np.sqrt(lam.max())
+    w = oracle.OracleRun(M, [[1.0]], [[kT]], hw, R, np.zeros((0, 2)), seed=38, burn_in=400, block_len=100,
+                         traces=True).run(8000)
+    mw, sw = w.estimates()
+    closed = kT * np.trace(np.linalg.inv(np.eye(N) - hw * hw * M / 4))
+    assert abs(mw[1] - closed) / sw[1] < 4.5
+    assert abs(mw[1] - kT * N) / sw[1] > 6.0   # the continuous-time kT N is excluded
