@@ -135,6 +135,12 @@ typedef struct {
     int32_t acc_pp;          /* != 0: also accumulate <p_i p_j> (the momentum form of Eq. 7:
                                 p_n sampled with q_n) for the same pairs and diagonal; the
                                 estimates then come in two blocks, q-q then p-p */
+    int32_t acc_trace;       /* != 0: also the trace estimators of Sec. I, appended after the
+                                pair blocks: sum_i <q_i^2> (Tr of the position response),
+                                <q^T M q> (= -<q . F>, Tr[M g(M)]) and, with acc_pp,
+                                sum_i <p_i^2> (the kinetic trace Tr f(M)).  Per-step sums are
+                                formed per row tile and folded in a fixed order once per
+                                chunk, so they are reproducible. */
 } fth_options;
 
 /* Fill *opt with defaults: seed 0, stream 0, FTH_FP32, burn_in 0,
@@ -161,7 +167,8 @@ fth_status fth_run(fth_ctx* ctx, int64_t nsteps, int32_t replicas);
 
 /* Number of estimates: npairs, plus n when acc_diag (pairs first, in input
  * order, then the diagonal in index order); twice that with acc_pp, the q-q
- * block followed by the p-p block in the same order. */
+ * block followed by the p-p block in the same order; then 2 (3 with acc_pp)
+ * trace estimators with acc_trace. */
 int64_t fth_num_outputs(const fth_ctx* ctx);
 
 /* Estimates of <q_i q_j> (and <p_i p_j> with acc_pp) and their standard errors (len >= fth_num_outputs,

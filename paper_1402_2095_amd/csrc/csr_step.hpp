@@ -31,7 +31,7 @@ namespace dev {
 // One row of one request: gather, noise, force, shared row update.
 template <typename Real, int NS, int RPT, bool NT>
 __device__ __forceinline__ void csr_row(const StepArgs<Real>& a, const StepInfo& si, int64_t i, const Real* qr,
-                                        Real* qw) {
+                                        Real* qw, double* trow) {
     using V = Vec<Real, RPT>;
     const int64_t R = a.R;
     // CSR entries gathered per batch: four keeps the kernel near 80 VGPRs (six waves
@@ -78,7 +78,7 @@ __device__ __forceinline__ void csr_row(const StepArgs<Real>& a, const StepInfo&
                 for (int m = 0; m < RPT; ++m) acc[m] = fmaR(vj[u], qj[u].v[m], acc[m]);
             }
     }
-    (void)finish_row<Real, NS, RPT, NT>(a, si, i, st, acc, xi, qw);
+    (void)finish_row<Real, NS, RPT, NT>(a, si, i, st, acc, xi, qw, trow);
 }
 
 // One row in the coded form: the row's 8 column codes and 8 value codes are
@@ -86,7 +86,7 @@ __device__ __forceinline__ void csr_row(const StepArgs<Real>& a, const StepInfo&
 // Slots keep the CSR order, so the sum is the plain form's, bit for bit.
 template <typename Real, int NS, int RPT, bool NT>
 __device__ __forceinline__ void coded_row(const StepArgs<Real>& a, const StepInfo& si, int64_t i, const Real* qr,
-                                          Real* qw, const int32_t* s_off, const Real* s_val) {
+                                          Real* qw, const int32_t* s_off, const Real* s_val, double* trow) {
     using V = Vec<Real, RPT>;
     const int64_t R = a.R;
     constexpr int G = 4;  // slots gathered per batch (two batches)
@@ -135,10 +135,12 @@ __device__ __forceinline__ void coded_row(const StepArgs<Real>& a, const StepInf
                 for (int m = 0; m < RPT; ++m) acc[m] = fmaR(vj[u], qj[u].v[m], acc[m]);
             }
     }
-    (void)finish_row<Real, NS, RPT, NT>(a, si, i, st, acc, xi, qw);
+    (void)finish_row<Real, NS, RPT, NT>(a, si, i, st, acc, xi, qw, trow);
 }
 
-template <typename Real, int NS, int RPT, bool NT, bool CODED>
+// TR: trace partials are kept (a separate instantiation, so the common form
+// carries none of their code or registers).
+template <typename Real, int NS, int RPT, bool NT, bool CODED, bool TR>
 __global__ __launch_bounds__(256) void csr_step_kernel(const StepArgs<Real> a, const int k) {
     const StepInfo si = step_info<Real, RPT>(a, k);
     const Real* __restrict__ qr = (si.n & 1) ? a.q1 : a.q0;
@@ -160,13 +162,20 @@ __global__ __launch_bounds__(256) void csr_step_kernel(const StepArgs<Real> a, c
     }
     const int64_t per = a.row_tiles_padded >> 3;
     const int64_t t = (b & 7) * per + (b >> 3);
-    if (t >= a.row_tiles) return;
+    if (t >= a.row_tiles) return;  // whole workgroup
     const int64_t i = t * per_block + si.slot;
-    if (i >= a.N) return;
-    if constexpr (CODED)
-        coded_row<Real, NS, RPT, NT>(a, si, i, qr, qw, s_off, s_val);
-    else
-        csr_row<Real, NS, RPT, NT>(a, si, i, qr, qw);
+    extern __shared__ double trl[];  // [rows of the tile][3], only with trace partials
+    double* trow = TR ? trl + si.slot * 3 : nullptr;
+    if (i < a.N) {
+        if constexpr (CODED)
+            coded_row<Real, NS, RPT, NT>(a, si, i, qr, qw, s_off, s_val, trow);
+        else
+            csr_row<Real, NS, RPT, NT>(a, si, i, qr, qw, trow);
+    }
+    if constexpr (TR) {
+        __syncthreads();
+        wave0_sum_rows(trl, min(int64_t(per_block), a.N - t * per_block), a.tpart + (int64_t(k) * a.tpart_w + t) * 3);
+    }
 }
 
 // ---------------------------------------------------------------- dispatch
@@ -206,20 +215,24 @@ const void* pick_kernel(const StepLaunch& L) {
     return L.nt ? pick_ns<K, Real, true>(L.ns, L.rpt) : pick_ns<K, Real, false>(L.ns, L.rpt);
 }
 
-template <typename Real, int NS, int RPT, bool NT>
-struct CsrKernel {
-    static const void* fn() { return reinterpret_cast<const void*>(&csr_step_kernel<Real, NS, RPT, NT, false>); }
-};
-
-// The coded form is instantiated for 4 and 8 replicas per thread only.
-template <typename Real, int NS, int RPT, bool NT>
-struct CodedKernel {
-    static const void* fn() {
-        if constexpr (RPT >= 4)
-            return reinterpret_cast<const void*>(&csr_step_kernel<Real, NS, RPT, NT, true>);
-        else
-            return nullptr;
-    }
+template <bool TR>
+struct CsrKernels {
+    template <typename Real, int NS, int RPT, bool NT>
+    struct Plain {
+        static const void* fn() {
+            return reinterpret_cast<const void*>(&csr_step_kernel<Real, NS, RPT, NT, false, TR>);
+        }
+    };
+    // The coded form is instantiated for 4 and 8 replicas per thread only.
+    template <typename Real, int NS, int RPT, bool NT>
+    struct Coded {
+        static const void* fn() {
+            if constexpr (RPT >= 4)
+                return reinterpret_cast<const void*>(&csr_step_kernel<Real, NS, RPT, NT, true, TR>);
+            else
+                return nullptr;
+        }
+    };
 };
 
 template <typename Real>
@@ -229,16 +242,22 @@ int launch_step_kernel(const void* fn, const StepArgs<Real>& a, const StepLaunch
     if (grid <= 0) return 0;
     if (grid > 0x7FFFFFFF) return -3;
     void* args[] = {const_cast<StepArgs<Real>*>(&a), &k};
-    hipError_t e = hipLaunchKernel(fn, dim3(unsigned(grid)), dim3(unsigned(L.block)), args, 0,
+    const size_t lds = a.tpart != nullptr ? size_t(L.block >> a.lg_tpr) * 3 * sizeof(double) : 0;
+    hipError_t e = hipLaunchKernel(fn, dim3(unsigned(grid)), dim3(unsigned(L.block)), args, lds,
                                    static_cast<hipStream_t>(stream));
     return e == hipSuccess ? 0 : -1;
 }
 
 }  // namespace dev
 
-template <typename Real>
+// TR: the instantiations with trace partials (kept in a file of their own so
+// the two halves compile in parallel).
+template <typename Real, bool TR>
 int launch_csr_step_impl(const StepArgs<Real>& a, const StepLaunch& L, int k, void* stream) {
-    const void* fn = L.coded ? dev::pick_kernel<dev::CodedKernel, Real>(L) : dev::pick_kernel<dev::CsrKernel, Real>(L);
+    if (TR != (a.tpart != nullptr)) return -4;
+    using KS = dev::CsrKernels<TR>;
+    const void* fn = L.coded ? dev::pick_kernel<KS::template Coded, Real>(L)
+                             : dev::pick_kernel<KS::template Plain, Real>(L);
     return dev::launch_step_kernel<Real>(fn, a, L, k, stream);
 }
 

@@ -4,7 +4,8 @@
 namespace fth {
 template <>
 int launch_csr_step<double>(const StepArgs<double>& a, const StepLaunch& L, int k, void* stream) {
-    return launch_csr_step_impl<double>(a, L, k, stream);
+    return a.tpart != nullptr ? launch_csr_step_traced<double>(a, L, k, stream)
+                              : launch_csr_step_impl<double, false>(a, L, k, stream);
 }
 
 namespace dev {

@@ -233,26 +233,13 @@ __global__ __launch_bounds__(256, 2) void gemm_f64_kernel(const DenseGemmArgs g)
 }
 
 // ------------------------------------------------------------- epilogue
+// One row of the dense epilogue: sum the split-K partials in slice order,
+// then the shared row update (and, in the split form, the bf16 split of q).
 template <typename Real, int NS, int RPT, bool NT>
-__global__ __launch_bounds__(256) void dense_epilogue_kernel(const StepArgs<Real> a, const int k) {
+__device__ __forceinline__ void dense_row(const StepArgs<Real>& a, const StepInfo& si, int64_t i, const Real* qr,
+                                          Real* qw, double* trow) {
     using V = Vec<Real, RPT>;
-    const StepInfo si = step_info<Real, RPT>(a, k);
-    const Real* __restrict__ qr = (si.n & 1) ? a.q1 : a.q0;
-    Real* __restrict__ qw = (si.n & 1) ? a.q0 : a.q1;
-    const int per_block = blockDim.x >> a.lg_tpr;
-    const int64_t b = blockIdx.x;
     const int64_t R = a.R;
-    if (b >= a.row_tiles_padded) {
-        const int64_t pk = (b - a.row_tiles_padded) * per_block + si.slot;
-        if (pk < a.npairs) pair_update<Real, RPT>(a, si, qr, pk);
-        return;
-    }
-    const int64_t per = a.row_tiles_padded >> 3;
-    const int64_t t = (b & 7) * per + (b >> 3);
-    if (t >= a.row_tiles) return;
-    const int64_t i = t * per_block + si.slot;
-    if (i >= a.N) return;
-
     const RowState<Real, NS, RPT> st = load_row<Real, NS, RPT, NT>(a, si, qr, i);
     constexpr int KMAX = 8;
     V pv[KMAX];
@@ -270,7 +257,7 @@ __global__ __launch_bounds__(256) void dense_epilogue_kernel(const StepArgs<Real
 #pragma unroll
             for (int m = 0; m < RPT; ++m) acc[m] = acc[m] + pv[s].v[m];
         }
-    const V qn = finish_row<Real, NS, RPT, NT>(a, si, i, st, acc, xi, qw);
+    const V qn = finish_row<Real, NS, RPT, NT>(a, si, i, st, acc, xi, qw, trow);
     if constexpr (sizeof(Real) == 4) {
         if (a.qt != nullptr) {
 #pragma unroll
@@ -279,16 +266,48 @@ __global__ __launch_bounds__(256) void dense_epilogue_kernel(const StepArgs<Real
     }
 }
 
-template <typename Real, int NS, int RPT, bool NT>
-struct DenseEpilogueKernel {
-    static const void* fn() { return reinterpret_cast<const void*>(&dense_epilogue_kernel<Real, NS, RPT, NT>); }
+template <typename Real, int NS, int RPT, bool NT, bool TR>
+__global__ __launch_bounds__(256) void dense_epilogue_kernel(const StepArgs<Real> a, const int k) {
+    const StepInfo si = step_info<Real, RPT>(a, k);
+    const Real* __restrict__ qr = (si.n & 1) ? a.q1 : a.q0;
+    Real* __restrict__ qw = (si.n & 1) ? a.q0 : a.q1;
+    const int per_block = blockDim.x >> a.lg_tpr;
+    const int64_t b = blockIdx.x;
+    if (b >= a.row_tiles_padded) {
+        const int64_t pk = (b - a.row_tiles_padded) * per_block + si.slot;
+        if (pk < a.npairs) pair_update<Real, RPT>(a, si, qr, pk);
+        return;
+    }
+    const int64_t per = a.row_tiles_padded >> 3;
+    const int64_t t = (b & 7) * per + (b >> 3);
+    if (t >= a.row_tiles) return;  // whole workgroup
+    const int64_t i = t * per_block + si.slot;
+    extern __shared__ double trl[];  // [rows of the tile][3], only with trace partials
+    double* trow = TR ? trl + si.slot * 3 : nullptr;
+    if (i < a.N) dense_row<Real, NS, RPT, NT>(a, si, i, qr, qw, trow);
+    if constexpr (TR) {
+        __syncthreads();
+        wave0_sum_rows(trl, min(int64_t(per_block), a.N - t * per_block), a.tpart + (int64_t(k) * a.tpart_w + t) * 3);
+    }
+}
+
+template <bool TR>
+struct DenseEpilogueKernels {
+    template <typename Real, int NS, int RPT, bool NT>
+    struct K {
+        static const void* fn() {
+            return reinterpret_cast<const void*>(&dense_epilogue_kernel<Real, NS, RPT, NT, TR>);
+        }
+    };
 };
 
 }  // namespace dev
 
 template <typename Real>
 int launch_dense_epilogue_impl(const StepArgs<Real>& a, const StepLaunch& L, int k, void* stream) {
-    return dev::launch_step_kernel<Real>(dev::pick_kernel<dev::DenseEpilogueKernel, Real>(L), a, L, k, stream);
+    const void* fn = a.tpart != nullptr ? dev::pick_kernel<dev::DenseEpilogueKernels<true>::template K, Real>(L)
+                                        : dev::pick_kernel<dev::DenseEpilogueKernels<false>::template K, Real>(L);
+    return dev::launch_step_kernel<Real>(fn, a, L, k, stream);
 }
 
 }  // namespace fth

@@ -466,6 +466,8 @@ fth::StepArgs<Real> step_args(fth_ctx* c) {
         }
     }
     a.flag = c->d_flag;
+    a.tpart = c->opt.acc_trace ? c->d_tpart : nullptr;
+    a.tpart_w = c->tpart_w;
     const int per_block = c->block / (c->R / c->rpt);
     a.row_tiles = (c->n + per_block - 1) / per_block;
     a.row_tiles_padded = (a.row_tiles + 7) / 8 * 8;
@@ -516,6 +518,54 @@ fth_status enqueue_step(fth_ctx* c, int k) {
     return FTH_OK;
 }
 
+// Rows of the widest tiling the current shape launches (one-step, blocked or small).
+int64_t trace_tiles(const fth_ctx* c) {
+    if (c->small) return 1;
+    const int per_block = c->block / (c->R / c->rpt);
+    int64_t w = (c->n + per_block - 1) / per_block;
+    if (c->tb_kt > 0) {
+        const int E = c->tb_block / (c->R / 4);
+        const int64_t T = E - 2 * int64_t(c->tb_kt) * c->band_w;
+        w = std::max(w, (c->n + T - 1) / T);
+    }
+    return w;
+}
+
+fth_status trace_prepare(fth_ctx* c, int K) {
+    if (!c->opt.acc_trace) return FTH_OK;
+    const int64_t w = trace_tiles(c);
+    if (K <= c->tpart_k && w <= c->tpart_w) return FTH_OK;
+    if (w > 0x7FFFFFFF) return fail(FTH_EUNSUPPORTED, "too many row tiles for trace partials");
+    const int nk = std::max(K, c->tpart_k);
+    const int nw = int(std::max<int64_t>(w, c->tpart_w));
+    if (c->gexec) {  // the captured graph holds the old buffers
+        (void)hipGraphExecDestroy(c->gexec);
+        c->gexec = nullptr;
+    }
+    HIP_OK(hipStreamSynchronize(c->stream));
+    c->dfree(reinterpret_cast<void*&>(c->d_tpart));
+    c->dfree(reinterpret_cast<void*&>(c->d_tsum));
+    const size_t pb = sizeof(double) * 3 * size_t(nk) * size_t(nw);
+    HIP_OK(c->dalloc(reinterpret_cast<void**>(&c->d_tpart), pb));
+    HIP_OK(hipMemset(c->d_tpart, 0, pb));
+    HIP_OK(c->dalloc(reinterpret_cast<void**>(&c->d_tsum), sizeof(double) * 3 * size_t(nk)));
+    c->tpart_k = nk;
+    c->tpart_w = nw;
+    return FTH_OK;
+}
+
+// Sum and fold the trace partials of the K steps just enqueued; the chunk's
+// first step is *d_step + shift.
+fth_status enqueue_trace_fold(fth_ctx* c, int K, int64_t shift) {
+    const int64_t o = c->n_out() - c->ntr();
+    const int64_t no = c->n_out();
+    if (fth::launch_trace_fold(c->d_tpart, c->d_tsum, K, c->tpart_w, c->ntr(), c->d_acc + o, c->d_acc + no + o,
+                               c->d_acc + 2 * no + o, c->d_step, shift, c->opt.burn_in, c->opt.block_len,
+                               c->stream) != 0)
+        return fail(FTH_EDEVICE, "trace fold launch failed");
+    return FTH_OK;
+}
+
 fth_status enqueue_small(fth_ctx* c, int64_t nsteps) {
     for (int64_t done = 0; done < nsteps;) {
         const int K = int(std::min<int64_t>(nsteps - done, 4096));
@@ -524,6 +574,10 @@ fth_status enqueue_small(fth_ctx* c, int64_t nsteps) {
                            : fth::launch_small_dense<float>(step_args<float>(c), step_launch(c), K, c->small_lds, c->stream);
         if (rc == -2) return fail(FTH_EUNSUPPORTED, "no kernel instantiated for ns=%d", c->ns);
         if (rc != 0) return fail(FTH_EDEVICE, "small-system kernel launch failed (%d)", rc);
+        if (c->opt.acc_trace) {  // the kernel has advanced the step counter by K already
+            fth_status st = enqueue_trace_fold(c, K, -int64_t(K));
+            if (st != FTH_OK) return st;
+        }
         done += K;
     }
     return FTH_OK;
@@ -534,7 +588,7 @@ bool tb_eligible(const fth_ctx* c, int KT, int block) {
     if (c->R < 4 || c->R > 256) return false;
     if (KT != 3 && KT != 5) return false;
     if (block != 256 && block != 512 && block != 1024) return false;
-    if (block > fth::tb_max_block(c->prec == FTH_FP64, c->ns)) return false;
+    if (block > fth::tb_max_block(c->prec == FTH_FP64, c->ns, c->opt.acc_pp || c->opt.acc_trace)) return false;
     const int E = block / (c->R / 4);
     const int64_t T = E - 2 * int64_t(KT) * c->band_w;
     return T >= 1 && 2 * T >= E;
@@ -608,6 +662,10 @@ fth_status enqueue_chunk(fth_ctx* c, int K) {
         fth_status st = enqueue_step(c, k);
         if (st != FTH_OK) return st;
     }
+    if (c->opt.acc_trace) {
+        fth_status st = enqueue_trace_fold(c, K, 0);
+        if (st != FTH_OK) return st;
+    }
     if (fth::launch_advance(c->d_step, K, c->stream) != 0) return fail(FTH_EDEVICE, "advance launch failed");
     return FTH_OK;
 }
@@ -659,7 +717,9 @@ std::map<TuneKey, TuneChoice>& tune_cache() {
 
 // Time K steps (enqueued without a graph) on the live state; us per step.
 fth_status time_chunk(fth_ctx* c, int K, double* us) {
-    fth_status st = enqueue_chunk(c, K);  // warm-up
+    fth_status st = trace_prepare(c, K);
+    if (st != FTH_OK) return st;
+    st = enqueue_chunk(c, K);  // warm-up
     if (st != FTH_OK) return st;
     HIP_OK(hipEventRecord(c->ev0, c->stream));
     st = enqueue_chunk(c, K);
@@ -772,6 +832,8 @@ fth_status run_enqueue(fth_ctx* c, int64_t nsteps) {
     fth_status st;
     int K = c->opt.steps_per_graph > 0 ? c->opt.steps_per_graph : kDefaultGraphSteps;
     if (c->tb_kt > 0) K = (K + c->tb_kt - 1) / c->tb_kt * c->tb_kt;  // whole blocked launches
+    st = trace_prepare(c, c->small ? 4096 : K);
+    if (st != FTH_OK) return st;
     if (c->d_qt && c->qt_dirty) {
         if (fth::launch_qt_from_q(static_cast<const float*>(c->d_q[c->step & 1]), c->d_qt, c->n, c->rows_pad, c->R,
                                   c->stream) != 0)
@@ -885,6 +947,7 @@ fth_status fth_create(const fth_matrix* M, const fth_gle* gle, double dt, const 
         return fail(FTH_EINVAL, "temporal_threads must be 0, 256, 512 or 1024");
     if (opt.coded_matrix != 0 && opt.coded_matrix != -1) return fail(FTH_EINVAL, "coded_matrix must be 0 or -1");
     if (opt.acc_pp != 0 && opt.acc_pp != 1) return fail(FTH_EINVAL, "acc_pp must be 0 or 1");
+    if (opt.acc_trace != 0 && opt.acc_trace != 1) return fail(FTH_EINVAL, "acc_trace must be 0 or 1");
     if (npairs < 0 || (npairs > 0 && !pairs)) return fail(FTH_EINVAL, "invalid pair list");
     for (int64_t k = 0; k < 2 * npairs; ++k)
         if (pairs[k] < 0 || pairs[k] >= M->n) return fail(FTH_EINVAL, "pair index out of range at %lld", (long long)k);
@@ -978,8 +1041,9 @@ fth_status fth_run(fth_ctx* c, int64_t nsteps, int32_t replicas) {
     if (nsteps == 0) return FTH_OK;
     HIP_OK(hipSetDevice(c->device));
     if (c->opt.temporal_steps > 0 && c->tb_kt == 0) {
-        const int tbb = c->opt.temporal_threads > 0 ? c->opt.temporal_threads
-                                                    : fth::tb_max_block(c->prec == FTH_FP64, c->ns);
+        const int tbb = c->opt.temporal_threads > 0
+                            ? c->opt.temporal_threads
+                            : fth::tb_max_block(c->prec == FTH_FP64, c->ns, c->opt.acc_pp || c->opt.acc_trace);
         if (!tb_eligible(c, c->opt.temporal_steps, tbb))
             return fail(FTH_EUNSUPPORTED,
                         "temporal blocking needs CSR with half-bandwidth <= %lld (%lld), <= 8 entries per row (%d), "

@@ -60,6 +60,10 @@ struct fth_ctx {
     int32_t* d_dict_off = nullptr;
     void* d_dict_val = nullptr;
     int32_t n_off = 0, n_val = 0;
+    // trace estimators: per-step, per-tile partials [tpart_k][tpart_w][3] and per-step sums
+    double* d_tpart = nullptr;
+    double* d_tsum = nullptr;
+    int32_t tpart_k = 0, tpart_w = 0;
     // temporal blocking of narrow-band CSR systems
     int64_t band_w = -1;   // half-bandwidth max |j - i| of the CSR pattern
     int max_row_nnz = 0;   // longest CSR row
@@ -100,7 +104,8 @@ struct fth_ctx {
     int64_t q_rows() const { return mfma() ? rows_pad : n; }
     // accumulated estimates: q-q pairs, q-q diagonal, then the same for p-p if kept
     int64_t n_kind() const { return npairs + (opt.acc_diag ? n : 0); }
-    int64_t n_out() const { return n_kind() * (opt.acc_pp ? 2 : 1); }
+    int ntr() const { return opt.acc_trace ? (opt.acc_pp ? 3 : 2) : 0; }  // trace estimators
+    int64_t n_out() const { return n_kind() * (opt.acc_pp ? 2 : 1) + ntr(); }
     size_t ps_bytes() const { return size_t(ps_rows) * size_t(R) * size_t(ns + 1) * real_bytes(); }
     // element offset of (row i, component c, replica r) in the (p, s) buffer:
     // groups of 2^ps_lg rows, each component of a group a contiguous [2^ps_lg][R] block
@@ -148,6 +153,9 @@ fth_status enqueue_chunk(fth_ctx* c, int K);
 // with the given workgroup size, and the device buffers it needs.
 bool tb_eligible(const fth_ctx* c, int KT, int block);
 fth_status tb_prepare(fth_ctx* c);
+// Trace partial buffers large enough for chunks of K steps in the current
+// launch shape (reallocated, and the graph dropped, when they must grow).
+fth_status trace_prepare(fth_ctx* c, int K);
 // Enqueue K steps of a small dense system (persistent kernel).
 fth_status enqueue_small(fth_ctx* c, int64_t nsteps);
 // Enqueue nsteps steps on the context's stream (graphs, tails, small path).

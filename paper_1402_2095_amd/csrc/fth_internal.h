@@ -74,6 +74,11 @@ struct StepArgs {
     double* dp_blk;
     double* dp_s1;
     double* dp_s2;
+    // trace partials (null if traces are not kept): for in-chunk step k and row
+    // tile t, tpart[(k * tpart_w + t) * 3 + c] = sum over the tile's rows and
+    // replicas of q^2 (c = 0), q (M q) (c = 1) and p^2 (c = 2)
+    double* tpart;
+    int32_t tpart_w;
     int32_t* flag;  // set to 1 when a non-finite state value appears
     int32_t ns;     // extra GLE momenta
     // launch geometry
@@ -116,8 +121,10 @@ struct DenseGemmArgs {
 // Largest workgroup of the temporally blocked step: a row's (p, s) and CSR
 // entries stay in registers for the whole launch, so larger NS (and FP64)
 // need the register file of fewer threads.
-constexpr int tb_max_block(bool f64, int ns) {
-    return f64 ? (ns == 0 ? 1024 : ns <= 4 ? 512 : 256) : (ns <= 4 ? 1024 : ns <= 9 ? 512 : 256);
+// Momentum-form and trace accumulators (xtra) need a few more registers.
+constexpr int tb_max_block(bool f64, int ns, bool xtra = false) {
+    const int b = f64 ? (ns == 0 ? 1024 : ns <= 4 ? 512 : 256) : (ns <= 4 ? 1024 : ns <= 9 ? 512 : 256);
+    return xtra && b > 512 ? 512 : b;
 }
 
 // Extra arguments of the temporally blocked sparse step.
@@ -142,6 +149,8 @@ struct PackedTile {
 // Launch wrappers (defined in the .hip files).
 template <typename Real>
 int launch_csr_step(const StepArgs<Real>& a, const StepLaunch& L, int k, void* stream);
+template <typename Real>  // the instantiations with trace partials
+int launch_csr_step_traced(const StepArgs<Real>& a, const StepLaunch& L, int k, void* stream);
 template <typename Real>
 int launch_dense_epilogue(const StepArgs<Real>& a, const StepLaunch& L, int k, void* stream);
 int launch_gemm_bf16x3(const DenseGemmArgs& g, void* stream);
@@ -149,6 +158,11 @@ int launch_gemm_f64(const DenseGemmArgs& g, void* stream);
 int launch_split_bf16(const float* m, uint16_t* hi, uint16_t* lo, int64_t count, void* stream);
 int launch_qt_from_q(const float* q, uint16_t* qt, int64_t N, int64_t rows_pad, int32_t R, void* stream);
 int launch_advance(int64_t* step_base, int64_t k, void* stream);
+// Trace estimators: sum the per-tile partials of K steps (fixed order), fold
+// them into the trace accumulators in step order and clear the partials.
+// Step k of the chunk is global step *step_base + shift + k.
+int launch_trace_fold(double* tpart, double* tsum, int K, int W, int ntr, double* blk, double* s1, double* s2,
+                      const int64_t* step_base, int64_t shift, int64_t burn_in, int64_t block_len, void* stream);
 // Temporally blocked step: one launch advances KT steps (KT odd); pairs follow.
 template <typename Real>
 int launch_tb_step(const StepArgs<Real>& a, const TbArgs<Real>& tb, const StepLaunch& L, int KT, int k, void* stream);

@@ -38,7 +38,7 @@ __global__ __launch_bounds__(256) void packed_csr_kernel(const StepArgs<float>* 
             continue;
         }
         const int64_t i = tl.index * per_block + si.slot;
-        if (i < a.N) csr_row<float, NS, RPT, NT>(a, si, i, qr, qw);
+        if (i < a.N) csr_row<float, NS, RPT, NT>(a, si, i, qr, qw, nullptr);  // no traces for packed requests
     }
 }
 

@@ -212,12 +212,62 @@ __device__ __forceinline__ bool ou_update(const Real* T, const Real* S, Real h, 
     return ok;
 }
 
+// Row sums behind the trace estimators: q^2, q (M q) and p^2 over the row's
+// replicas (identical in every lane of the row); acc holds (M q)_i.
+template <typename Real, int NS, int RPT>
+__device__ __forceinline__ void row_traces(const RowState<Real, NS, RPT>& st, const Real (&acc)[RPT], int tpr,
+                                           double (&tr)[3]) {
+    double qm = 0.0;
+#pragma unroll
+    for (int m = 0; m < RPT; ++m) qm += double(st.q.v[m]) * double(acc[m]);
+    tr[0] = dot_row<Real, RPT>(st.q, st.q, tpr);
+    tr[1] = group_sum(qm, tpr);
+    tr[2] = dot_row<Real, RPT>(st.p, st.p, tpr);
+}
+
+// Sum of the rows' trace slots trl[0..nrows)[3] by wave 0, in a fixed order
+// (strided per lane, then an xor butterfly); call after a barrier.  Lane 0
+// writes the three sums to out.
+__device__ __forceinline__ void wave0_sum_rows(const double* trl, int64_t nrows, double* out) {
+    if (threadIdx.x >= 64) return;
+    double v[3] = {0.0, 0.0, 0.0};
+    for (int64_t r = threadIdx.x; r < nrows; r += 64)
+        for (int c = 0; c < 3; ++c) v[c] += trl[r * 3 + c];
+    for (int c = 0; c < 3; ++c)
+        for (int off = 32; off > 0; off >>= 1) v[c] += __shfl_xor(v[c], off, 64);
+    if (threadIdx.x == 0)
+        for (int c = 0; c < 3; ++c) out[c] = v[c];
+}
+
+// Workgroup sum of three values held by the first lane of every row (other
+// lanes pass 0), in a fixed order: lanes of a wave by xor butterfly, then the
+// waves in index order.  Every thread of the workgroup must call it.
+__device__ __forceinline__ void workgroup_sum3(double (&v)[3], double* red /* [16][3] LDS */) {
+#pragma unroll
+    for (int c = 0; c < 3; ++c)
+        for (int off = 32; off > 0; off >>= 1) v[c] += __shfl_xor(v[c], off, 64);
+    const int wave = int(threadIdx.x) >> 6, lane = int(threadIdx.x) & 63;
+    if (lane == 0)
+        for (int c = 0; c < 3; ++c) red[wave * 3 + c] = v[c];
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        const int nw = int(blockDim.x + 63) >> 6;
+        for (int c = 0; c < 3; ++c) {
+            double s = 0.0;
+            for (int w = 0; w < nw; ++w) s += red[w * 3 + c];
+            v[c] = s;
+        }
+    }
+}
+
 // Diagonal accumulation, kicks, exact OU step, drift and stores.  Returns
-// q_{n+1} for the thread's replicas.
+// q_{n+1} for the thread's replicas.  With trace partials kept, the row's
+// trace sums go to trow[0..2] (an LDS slot of the row) before the update, so
+// nothing extra stays live through it.
 template <typename Real, int NS, int RPT, bool NT>
 __device__ __forceinline__ Vec<Real, RPT> finish_row(const StepArgs<Real>& a, const StepInfo& si, int64_t i,
                                                      const RowState<Real, NS, RPT>& st, const Real (&acc)[RPT],
-                                                     const Real (&xi)[NS + 1][RPT], Real* qw) {
+                                                     const Real (&xi)[NS + 1][RPT], Real* qw, double* trow) {
     constexpr int D = NS + 1;
     const int64_t R = a.R;
     if (a.dblk != nullptr) {
@@ -227,6 +277,12 @@ __device__ __forceinline__ Vec<Real, RPT> finish_row(const StepArgs<Real>& a, co
     if (a.dp_blk != nullptr) {
         const double y = dot_row<Real, RPT>(st.p, st.p, si.tpr);
         if (si.rq == 0 && si.acc_on) acc_update(a.dp_blk, a.dp_s1, a.dp_s2, i, y, si.close);
+    }
+    if (trow != nullptr) {
+        double tr[3];
+        row_traces<Real, NS, RPT>(st, acc, si.tpr, tr);
+        if (si.rq == 0)
+            for (int c = 0; c < 3; ++c) trow[c] = tr[c];
     }
     RowState<Real, NS, RPT> nx;
     const bool ok = ou_update<Real, NS, RPT>(a.TS, a.TS + D * D, a.h, a.hh, st, acc, xi, nx);

@@ -73,8 +73,10 @@ __global__ __launch_bounds__(1024) void small_dense_kernel(const StepArgs<Real> 
     bool ok = true;
     __syncthreads();
 
+    __shared__ double red[16 * 3];
     for (int k = 0; k < K; ++k) {
         const int64_t n = n0 + k;
+        double tr[3] = {0.0, 0.0, 0.0};
         const bool acc_on = n >= a.burn_in;
         const bool close = acc_on && ((n - a.burn_in + 1) % a.block_len) == 0;
         const Real* qr = qb + (n & 1) * N * R;
@@ -127,11 +129,18 @@ __global__ __launch_bounds__(1024) void small_dense_kernel(const StepArgs<Real> 
             for (int c = 0; c <= NS; ++c)
                 normals<Real, RPT>(a.key0, a.key1, a.stream, uint32_t(i), uint32_t(n), uint32_t(c), uint32_t(r0),
                                    xi[c]);
+            if (a.tpart != nullptr) row_traces<Real, NS, RPT>(st, acc, tpr, tr);
             RowState<Real, NS, RPT> nx;
             ok = ou_update<Real, NS, RPT>(T, S, a.h, a.hh, st, acc, xi, nx) && ok;
             store_vec<Real, RPT>(qw + i * R + r0, nx.q);
             if (pp_pairs) store_vec<Real, RPT>(pb + ((n + 1) & 1) * N * R + i * R + r0, nx.p);
             st = nx;
+        }
+        if (a.tpart != nullptr) {  // one partial per step (a single tile)
+            if (!active || rq != 0) tr[0] = tr[1] = tr[2] = 0.0;
+            workgroup_sum3(tr, red);
+            if (tid == 0)
+                for (int c = 0; c < 3; ++c) a.tpart[int64_t(k) * a.tpart_w * 3 + c] = tr[c];
         }
         __syncthreads();
     }

@@ -6,7 +6,8 @@
 // exact if its neighbours were exact before it, so the exact region shrinks
 // by w rows on each side per step; after KT steps it is exactly the output
 // range.  Rows are computed only while they can still reach the output.
-//   - q of the extended range lives in LDS (two buffers, q_n and q_{n+1});
+//   - q of the extended range lives in LDS (two buffers, q_n and q_{n+1}),
+//     followed, with trace estimators, by two [T][3] buffers of row sums;
 //   - p, s and the CSR row live in registers for the whole launch;
 //   - the diagonal block sum of an output row lives in a register; s1 / s2
 //     are updated in global memory only when a block closes;
@@ -28,8 +29,10 @@
 namespace fth {
 namespace dev {
 
-template <typename Real, int NS, int RPT, int KT>
-__global__ __launch_bounds__(tb_max_block(sizeof(Real) == 8, NS)) void tb_step_kernel(const StepArgs<Real> a, const TbArgs<Real> tb, const int k) {
+// XTRA: momentum-form or trace accumulators are kept (compiled out otherwise,
+// which keeps the common form within the register budget of 1024 threads).
+template <typename Real, int NS, int RPT, int KT, bool XTRA>
+__global__ __launch_bounds__(tb_max_block(sizeof(Real) == 8, NS, XTRA)) void tb_step_kernel(const StepArgs<Real> a, const TbArgs<Real> tb, const int k) {
     extern __shared__ double tb_smem[];
     Real* qlds = reinterpret_cast<Real*>(tb_smem);  // [2][E][R]
     constexpr int G = 8;                             // CSR entries per row (at most)
@@ -73,7 +76,7 @@ __global__ __launch_bounds__(tb_max_block(sizeof(Real) == 8, NS)) void tb_step_k
         }
         store_vec<Real, RPT>(qlds + int64_t(e) * R + r0, st.q);
         if (output && a.dblk != nullptr && rq == 0) blk = a.dblk[i];
-        if (output && a.dp_blk != nullptr && rq == 0) blkp = a.dp_blk[i];
+        if (XTRA && output && a.dp_blk != nullptr && rq == 0) blkp = a.dp_blk[i];
         if (output && tb.pair_slot != nullptr) pslot = tb.pair_slot[i];
     }
     const Real* T_ = a.TS;
@@ -81,6 +84,10 @@ __global__ __launch_bounds__(tb_max_block(sizeof(Real) == 8, NS)) void tb_step_k
     bool ok = true;
     __syncthreads();
 
+    // trace sums of the output rows, [step parity][T][3] after q in LDS: written
+    // by the first lane of each row, summed by wave 0 after the step's barrier
+    // while the other waves go on (the next step writes the other half)
+    double* trl = reinterpret_cast<double*>(qlds + int64_t(2) * E * R);
 #pragma unroll 1
     for (int s = 0; s < KT; ++s) {
         const int64_t n = n0 + s;
@@ -100,7 +107,7 @@ __global__ __launch_bounds__(tb_max_block(sizeof(Real) == 8, NS)) void tb_step_k
                     }
                 }
             }
-            if (a.dp_blk != nullptr) {
+            if (XTRA && a.dp_blk != nullptr) {
                 const double y = dot_row<Real, RPT>(st.p, st.p, tpr);
                 if (rq == 0 && acc_on) {
                     blkp = blkp + y;
@@ -113,7 +120,7 @@ __global__ __launch_bounds__(tb_max_block(sizeof(Real) == 8, NS)) void tb_step_k
             }
             if (pslot >= 0) {
                 store_vec<Real, RPT>(tb.snap + (int64_t(2 * s) * tb.nslots + pslot) * R + r0, st.q);
-                if (a.pp_blk != nullptr)
+                if (XTRA && a.pp_blk != nullptr)
                     store_vec<Real, RPT>(tb.snap + (int64_t(2 * s + 1) * tb.nslots + pslot) * R + r0, st.p);
             }
         }
@@ -134,12 +141,28 @@ __global__ __launch_bounds__(tb_max_block(sizeof(Real) == 8, NS)) void tb_step_k
             for (int c = 0; c <= NS; ++c)
                 normals<Real, RPT>(a.key0, a.key1, a.stream, uint32_t(i), uint32_t(n), uint32_t(c), uint32_t(r0),
                                    xi[c]);
+            if (XTRA && output && a.tpart != nullptr) {
+                double tr[3];
+                row_traces<Real, NS, RPT>(st, acc, tpr, tr);
+                if (rq == 0)
+                    for (int c = 0; c < 3; ++c) trl[((s & 1) * T + (e - H)) * 3 + c] = tr[c];
+            }
             RowState<Real, NS, RPT> nx;
             ok = ou_update<Real, NS, RPT>(T_, S_, a.h, a.hh, st, acc, xi, nx) && ok;
             store_vec<Real, RPT>(nxt + int64_t(e) * R + r0, nx.q);
             st = nx;
         }
         __syncthreads();
+        if (XTRA && a.tpart != nullptr && threadIdx.x < 64) {  // wave 0: the T output rows in a fixed order
+            const int64_t nout = min(int64_t(T), a.N - t * T);
+            double v[3] = {0.0, 0.0, 0.0};
+            for (int64_t r = threadIdx.x; r < nout; r += 64)
+                for (int c = 0; c < 3; ++c) v[c] += trl[((s & 1) * T + r) * 3 + c];
+            for (int c = 0; c < 3; ++c)
+                for (int off = 32; off > 0; off >>= 1) v[c] += __shfl_xor(v[c], off, 64);
+            if (threadIdx.x == 0)
+                for (int c = 0; c < 3; ++c) a.tpart[(int64_t(k + s) * a.tpart_w + t) * 3 + c] = v[c];
+        }
     }
     if (output) {
         store_state<Real, RPT, true>(qgo + i * R + r0, st.q);
@@ -149,7 +172,7 @@ __global__ __launch_bounds__(tb_max_block(sizeof(Real) == 8, NS)) void tb_step_k
 #pragma unroll
         for (int c = 0; c < NS; ++c) store_state<Real, RPT, true>(psrow + (c + 1) * cs, st.s[c]);
         if (a.dblk != nullptr && rq == 0) a.dblk[i] = blk;
-        if (a.dp_blk != nullptr && rq == 0) a.dp_blk[i] = blkp;
+        if (XTRA && a.dp_blk != nullptr && rq == 0) a.dp_blk[i] = blkp;
         if (!ok) atomicOr(a.flag, 1);
     }
 }
@@ -180,20 +203,20 @@ __global__ __launch_bounds__(256) void tb_pairs_kernel(const StepArgs<Real> a, c
     }
 }
 
-template <typename Real, int KT>
+template <typename Real, int KT, bool X>
 const void* pick_tb_ns(int ns) {
     switch (ns) {
-        case 0: return reinterpret_cast<const void*>(&tb_step_kernel<Real, 0, 4, KT>);
-        case 1: return reinterpret_cast<const void*>(&tb_step_kernel<Real, 1, 4, KT>);
-        case 2: return reinterpret_cast<const void*>(&tb_step_kernel<Real, 2, 4, KT>);
-        case 3: return reinterpret_cast<const void*>(&tb_step_kernel<Real, 3, 4, KT>);
-        case 4: return reinterpret_cast<const void*>(&tb_step_kernel<Real, 4, 4, KT>);
-        case 5: return reinterpret_cast<const void*>(&tb_step_kernel<Real, 5, 4, KT>);
-        case 6: return reinterpret_cast<const void*>(&tb_step_kernel<Real, 6, 4, KT>);
-        case 7: return reinterpret_cast<const void*>(&tb_step_kernel<Real, 7, 4, KT>);
-        case 8: return reinterpret_cast<const void*>(&tb_step_kernel<Real, 8, 4, KT>);
-        case 9: return reinterpret_cast<const void*>(&tb_step_kernel<Real, 9, 4, KT>);
-        case 10: return reinterpret_cast<const void*>(&tb_step_kernel<Real, 10, 4, KT>);
+        case 0: return reinterpret_cast<const void*>(&tb_step_kernel<Real, 0, 4, KT, X>);
+        case 1: return reinterpret_cast<const void*>(&tb_step_kernel<Real, 1, 4, KT, X>);
+        case 2: return reinterpret_cast<const void*>(&tb_step_kernel<Real, 2, 4, KT, X>);
+        case 3: return reinterpret_cast<const void*>(&tb_step_kernel<Real, 3, 4, KT, X>);
+        case 4: return reinterpret_cast<const void*>(&tb_step_kernel<Real, 4, 4, KT, X>);
+        case 5: return reinterpret_cast<const void*>(&tb_step_kernel<Real, 5, 4, KT, X>);
+        case 6: return reinterpret_cast<const void*>(&tb_step_kernel<Real, 6, 4, KT, X>);
+        case 7: return reinterpret_cast<const void*>(&tb_step_kernel<Real, 7, 4, KT, X>);
+        case 8: return reinterpret_cast<const void*>(&tb_step_kernel<Real, 8, 4, KT, X>);
+        case 9: return reinterpret_cast<const void*>(&tb_step_kernel<Real, 9, 4, KT, X>);
+        case 10: return reinterpret_cast<const void*>(&tb_step_kernel<Real, 10, 4, KT, X>);
         default: return nullptr;
     }
 }
@@ -205,11 +228,15 @@ template <typename Real>
 int launch_tb_step_impl(const StepArgs<Real>& a, const TbArgs<Real>& tb, const StepLaunch& L, int KT, int k,
                         void* stream) {
     if (L.rpt != 4) return -2;
-    const void* fn = KT == 3 ? dev::pick_tb_ns<Real, 3>(L.ns) : KT == 5 ? dev::pick_tb_ns<Real, 5>(L.ns) : nullptr;
+    const bool x = a.pp_blk != nullptr || a.dp_blk != nullptr || a.tpart != nullptr;
+    const void* fn = KT == 3 ? (x ? dev::pick_tb_ns<Real, 3, true>(L.ns) : dev::pick_tb_ns<Real, 3, false>(L.ns))
+                     : KT == 5 ? (x ? dev::pick_tb_ns<Real, 5, true>(L.ns) : dev::pick_tb_ns<Real, 5, false>(L.ns))
+                               : nullptr;
     if (fn == nullptr) return -2;
     const int block = tb.E << a.lg_tpr;
-    if (block > tb_max_block(sizeof(Real) == 8, L.ns) || block % 64 != 0) return -3;
-    const size_t lds = size_t(2) * size_t(tb.E) * size_t(a.R) * sizeof(Real);
+    if (block > tb_max_block(sizeof(Real) == 8, L.ns, x) || block % 64 != 0) return -3;
+    const size_t lds = size_t(2) * size_t(tb.E) * size_t(a.R) * sizeof(Real) +
+                       (a.tpart != nullptr ? size_t(2) * size_t(tb.T) * 3 * sizeof(double) : 0);
     StepArgs<Real> aa = a;
     TbArgs<Real> tt = tb;
     int kk = k;

@@ -1,5 +1,6 @@
 """GPU parity of the momentum form of the estimator (Eq. 7: <p_i p_j>, p_n
-sampled with q_n), kept beside the position form with acc_pp.
+sampled with q_n), kept beside the position form with acc_pp, and of the
+trace estimators of Sec. I (sum_i <q_i^2>, <q^T M q>, sum_i <p_i^2>).
 
 Every step form is covered: the one-step sparse kernel (plain CSR and the
 coded form), the dense epilogue (FP64 and split-BF16x3), the persistent
@@ -27,14 +28,15 @@ def normwise(a, b):
     return float(np.max(np.abs(a - b)) / den) if den > 0 else float(np.max(np.abs(a)))
 
 
-def run_parity(M, h, g, R, prec, pairs, label, expect_kernel, steps=(1, 10, 100, 1000)):
+def run_parity(M, h, g, R, prec, pairs, label, expect_kernel, steps=(1, 10, 100, 1000), temporal_steps=-1):
     n = M.shape[0] if isinstance(M, np.ndarray) else M.n
     sol = fth.Solver(M, g.A_p, g.C_p, h, pairs=pairs, replicas=R, precision=prec, seed=77, stream_id=4,
-                     burn_in=3, block_len=9, acc_diag=True, acc_pp=True, steps_per_graph=16, temporal_steps=-1)
+                     burn_in=3, block_len=9, acc_diag=True, acc_pp=True, acc_trace=True, steps_per_graph=16,
+                     temporal_steps=temporal_steps)
     Mo = M.astype(np.float64) if isinstance(M, np.ndarray) else M
     orc = oracle.OracleRun(Mo, g.A_p, g.C_p, h, R, np.concatenate([pairs, fi.diag_pairs(n)]), seed=77, stream=4,
-                           burn_in=3, block_len=9, pp=True)
-    assert fth.fth_num_outputs(sol.ctx) == 2 * (len(pairs) + n)
+                           burn_in=3, block_len=9, pp=True, traces=True)
+    assert fth.fth_num_outputs(sol.ctx) == 2 * (len(pairs) + n) + 3
     done = 0
     for target in steps:
         sol.run(target - done)
@@ -43,9 +45,12 @@ def run_parity(M, h, g, R, prec, pairs, label, expect_kernel, steps=(1, 10, 100,
         blk, s1, s2, nb, step = sol.accumulators()
         A = len(pairs) + n
         errs = {"acc_q": normwise((s1 + blk)[:A], (orc.s1 + orc.blk)[:A]),
-                "acc_p": normwise((s1 + blk)[A:], (orc.s1 + orc.blk)[A:])}
+                "acc_p": normwise((s1 + blk)[A:2 * A], (orc.s1 + orc.blk)[A:2 * A])}
+        for c, name in enumerate(("tr_qq", "tr_qMq", "tr_pp")):
+            errs[name] = normwise((s1 + blk)[2 * A + c], (orc.s1 + orc.blk)[2 * A + c])
         if nb:
-            errs["s2_p"] = normwise(s2[A:], orc.s2[A:])
+            errs["s2_p"] = normwise(s2[A:2 * A], orc.s2[A:2 * A])
+            errs["s2_tr"] = normwise(s2[2 * A:], orc.s2[2 * A:])
         print(f"  [{label}] step {done}: " + " ".join(f"{k}={v:.2e}" for k, v in errs.items()), flush=True)
         for k, v in errs.items():
             assert v <= TOL[prec], (label, done, k, v)
@@ -82,6 +87,13 @@ def test_small_momentum_parity(R, prec):
     g = fi.GLE(4, g.A_p * 3.0, g.C_p * 3.0)  # alpha = gamma = 3: window moves to lambda in [0.9, 109]
     run_parity(M, fi.dt_rule(lam.max()), g, R, prec, fi.random_pairs(60, 20, 14), "small", "small_dense_kernel",
                steps=(1, 10, 100, 1000, 3000))
+
+
+@pytest.mark.parametrize("kt", [3, 5])
+def test_blocked_momentum_and_traces_parity(kt):
+    M = fi.banded_spd_csr(3001, 19, dtype=np.float64)
+    run_parity(M, fi.dt_rule(fi.gershgorin_max(M)), fi.load_gle("fermi_b20_ns4"), 32, fth.FTH_FP64,
+               fi.random_pairs(M.n, 40, 18), f"blocked KT={kt}", "tb_step_kernel", temporal_steps=kt)
 
 
 @pytest.mark.parametrize("kt", [3, 5])
@@ -139,3 +151,29 @@ def test_momentum_estimates_match_exact_response():
     print(f"[pp white] max|z| {np.max(np.abs(z)):.2f}", flush=True)
     assert np.max(np.abs(z)) < 5.5
     assert np.max(np.abs((est[300:] - kT) / se[300:])) > 6.0
+
+
+def test_traces_reproducible_and_exact():
+    """Trace sums are folded in a fixed order: graph and direct runs agree bit
+    for bit.  Statistically they match the eigenvalue sums of the exact
+    responses on the periodic 12^3 Laplacian: Tr gh, Tr[M gh], Tr gh_p."""
+    n_side = 12
+    M = fi.laplacian3d_csr(n_side, 0.1)
+    g = fi.load_gle("invsqrt_ns4")
+    h = fi.dt_rule(fi.laplacian3d_lambda_max(n_side, 0.1))
+    kw = dict(replicas=16, seed=21, burn_in=100, block_len=50, acc_pp=True, acc_trace=True)
+    a = fth.Solver(M, g.A_p, g.C_p, h, steps_per_graph=32, **kw).run(1000)
+    b = fth.Solver(M, g.A_p, g.C_p, h, steps_per_graph=1000000, **kw).run(1000)
+    for x, y in zip(a.accumulators()[:3], b.accumulators()[:3]):
+        assert np.array_equal(x, y)
+    a.run(39000)
+    est, se, _ = a.read()
+    lam = exact.laplacian_eigs(n_side, 0.1).ravel()
+    T, S = oracle.propagator(g.A_p, g.C_p, h)
+    ghl = exact.gh(np.unique(np.round(lam, 12)), g.A_p, g.C_p, h, T, S)
+    ghpl = exact.gh_p(np.unique(np.round(lam, 12)), g.A_p, g.C_p, h, T, S)
+    uniq, inv = np.unique(np.round(lam, 12), return_inverse=True)
+    ref = np.array([ghl[inv].sum(), (lam * ghl[inv]).sum(), ghpl[inv].sum()])
+    z = (est - ref) / se
+    print(f"[traces] est {est}, ref {ref}, z {z}", flush=True)
+    assert np.max(np.abs(z)) < 5.0
