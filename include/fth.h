@@ -141,6 +141,16 @@ typedef struct {
                                 sum_i <p_i^2> (the kinetic trace Tr f(M)).  Per-step sums are
                                 formed per row tile and folded in a fixed order once per
                                 chunk, so they are reproducible. */
+    /* Spectral map (Sec. I, scaling of the GLE and of M): the dynamics run on
+       M' = scale_r M + scale_m I with A'_p = gle_alpha A_p, C'_p = gle_gamma C_p,
+       so the estimates are those of the transformed problem (fth_unscale maps
+       them back for the targets where that is possible).  0 for scale_r,
+       gle_alpha or gle_gamma means 1.  M' is formed on the host at create and
+       must itself pass validation (a shift needs stored diagonal entries). */
+    double scale_r;
+    double scale_m;
+    double gle_alpha;
+    double gle_gamma;
 } fth_options;
 
 /* Fill *opt with defaults: seed 0, stream 0, FTH_FP32, burn_in 0,
@@ -225,6 +235,38 @@ fth_status fth_propagator(const fth_gle* gle, double dt, double* T, double* S);
 fth_status fth_noise_sample(uint64_t seed, uint32_t stream, int64_t count, const uint32_t* i,
                             const uint32_t* r, const uint32_t* n, const uint32_t* j,
                             int32_t precision, double* out, uint32_t* raw);
+
+/* ---- spectral map helpers (host only, Sec. I scaling paragraph) ---- */
+
+/* r and m of M' = r M + m I that send a spectrum [e_min, e_max] onto the
+ * window [w_min, w_max] of a fitted GLE:
+ *   r = (w_min - w_max) / (e_min - e_max),
+ *   m = (e_min w_max - e_max w_min) / (e_min - e_max),
+ * so that r e_min + m = w_min and r e_max + m = w_max.
+ * FTH_EINVAL unless e_min < e_max and w_min < w_max (all finite). */
+fth_status fth_spectral_map(double e_min, double e_max, double w_min, double w_max, double* r, double* m);
+
+/* Gershgorin interval [lo, hi] containing every eigenvalue of M (symmetric). */
+fth_status fth_gershgorin(const fth_matrix* M, double* lo, double* hi);
+
+/* Targets whose value on M can be recovered from the transformed problem. */
+typedef enum {
+    FTH_TARGET_INVSQRT = 0, /* f(x) = x^-1/2: needs m = 0; f(M) = sqrt(r') f(M') */
+    FTH_TARGET_LN = 1,      /* f(x) = ln x:   needs m = 0; f(M) = f(M') - ln(r') I */
+    FTH_TARGET_EXPNEG = 2   /* f(x) = e^-x:   exp(-r' M) = e^m' f(M') */
+} fth_target;
+
+/* Map position-form estimates of a run with (r, m, alpha, gamma) back to
+ * f(M).  The q-response of the scaled GLE is (gamma / alpha^2) g(M' / alpha^2)
+ * (Sec. I), so first est *= alpha^2 / gamma and r' = r / alpha^2,
+ * m' = m / alpha^2; then the target's identity above.  kind_weight[k] is the
+ * number of identity entries output k contains: 0 for an off-diagonal
+ * element, 1 for a diagonal element, n for a trace over n rows (the ln shift
+ * is weighted by it).  est and se (either may be NULL) are updated in place;
+ * se scales like est.  FTH_EINVAL for an unknown target, a non-positive r'
+ * or a map the target cannot undo. */
+fth_status fth_unscale(int32_t target, double r, double m, double alpha, double gamma, int64_t count,
+                       const double* kind_weight, double* est, double* se);
 
 /* Device bytes a context with these parameters allocates. */
 size_t fth_footprint_bytes(const fth_matrix* M, int32_t ns, int32_t replicas,

@@ -88,6 +88,10 @@ def make_target(kind: str, **kw):
     if kind == "fermi":
         beta, mu = kw["beta"], kw["mu"]
         return (lambda x: 0.5 * (1.0 - np.tanh(0.5 * beta * (x - mu)))), kw.get("delta", 1e-3)
+    if kind == "ln":        # positive on a window above 1 (the method needs f > 0, Sec. I)
+        return (lambda x: np.log(x)), None
+    if kind == "expneg":    # exp(-x)
+        return (lambda x: np.exp(-x)), None
     raise ValueError(kind)
 
 
@@ -203,21 +207,27 @@ def main():
     here = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
     out_dir = os.path.join(here, "fth_inputs", "gle")
     os.makedirs(out_dir, exist_ok=True)
-    lam_lo, lam_hi = 0.1, 12.1          # spectrum of the 64^3 periodic Laplacian + 0.1
-    h = 0.1 / math.sqrt(lam_hi)
+    lap = (0.1, 12.1)                   # spectrum of the 64^3 periodic Laplacian + 0.1
+    # name, target, ns, target parameters, window, fit settings (those that produced the files)
+    fermi_opts = dict(starts=12, seed=10, w_tau=0.1, max_nfev=300)
+    smooth_opts = dict(starts=8, seed=0, w_tau=0.005, max_nfev=4000)
     jobs = [
-        ("invsqrt_ns4", "invsqrt", 4, {}),
-        ("fermi_b20_ns4", "fermi", 4, {"beta": 20.0, "mu": 6.1, "delta": 1e-2}),
+        ("invsqrt_ns4", "invsqrt", 4, {}, lap, smooth_opts),
+        ("fermi_b20_ns4", "fermi", 4, {"beta": 20.0, "mu": 6.1, "delta": 1e-2}, lap, fermi_opts),
+        ("fermi_b5_ns4", "fermi", 4, {"beta": 5.0, "mu": 6.1, "delta": 1e-2}, lap, fermi_opts),
+        # ln on a window above 1: a spectrum [e_lo, e_hi] with e_hi / e_lo <= 500 maps into it
+        # with M' = r M (the undo is ln M = ln M' - ln r)
+        ("ln_ns4", "ln", 4, {}, (1.2, 600.0), smooth_opts),
+        # exp(-x): a Gershgorin interval of width <= 6 maps into it with M' = M + m I
+        ("expneg_ns4", "expneg", 4, {}, (0.1, 6.1), smooth_opts),
     ]
     only = sys.argv[1:]
-    for name, kind, ns, kw in jobs:
+    for name, kind, ns, kw, (lam_lo, lam_hi), opts in jobs:
         if only and name not in only:
             continue
+        h = 0.1 / math.sqrt(lam_hi)
         t0 = time.time()
         print(f"fitting {name}", flush=True)
-        # settings that produced the committed files
-        opts = (dict(starts=12, seed=10, w_tau=0.1, max_nfev=300) if kind == "fermi"
-                else dict(starts=8, seed=0, w_tau=0.005, max_nfev=4000))
         Ap, Cp, _, f = fit(kind, ns, lam_lo, lam_hi, **opts, **kw)
         rep = report(kind, Ap, Cp, lam_lo, lam_hi, f, h, **kw)
         print(f"  {name}: {rep}  ({time.time() - t0:.1f}s)", flush=True)

@@ -926,17 +926,36 @@ size_t fth_footprint_bytes(const fth_matrix* M, int32_t ns, int32_t R, int64_t n
     return bytes;
 }
 
-fth_status fth_create(const fth_matrix* M, const fth_gle* gle, double dt, const int32_t* pairs, int64_t npairs,
+fth_status fth_create(const fth_matrix* M_in, const fth_gle* gle_in, double dt, const int32_t* pairs, int64_t npairs,
                       const fth_options* opt_in, fth_ctx** out) {
     g_last_error.clear();
     if (!out) return fail(FTH_EINVAL, "out must not be NULL");
     *out = nullptr;
-    if (!M || !gle) return fail(FTH_EINVAL, "M and gle must not be NULL");
+    if (!M_in || !gle_in) return fail(FTH_EINVAL, "M and gle must not be NULL");
     fth_options opt;
     fth_default_options(&opt);
     if (opt_in) opt = *opt_in;
-    if (M->n < 1 || M->n > 0xFFFFFFFFll) return fail(FTH_EINVAL, "n must be in [1, 2^32)");
-    if (M->format != FTH_CSR && M->format != FTH_DENSE) return fail(FTH_EINVAL, "unknown matrix format");
+    if (M_in->n < 1 || M_in->n > 0xFFFFFFFFll) return fail(FTH_EINVAL, "n must be in [1, 2^32)");
+    if (M_in->format != FTH_CSR && M_in->format != FTH_DENSE) return fail(FTH_EINVAL, "unknown matrix format");
+    // spectral map: M' = r M + m I, A'_p = alpha A_p, C'_p = gamma C_p (identity by default)
+    const double sr = opt.scale_r == 0.0 ? 1.0 : opt.scale_r, sm = opt.scale_m;
+    const double ga = opt.gle_alpha == 0.0 ? 1.0 : opt.gle_alpha, gg = opt.gle_gamma == 0.0 ? 1.0 : opt.gle_gamma;
+    fth_matrix M_map;
+    std::vector<double> map_store;
+    const fth_matrix* M = M_in;
+    if (sr != 1.0 || sm != 0.0) {
+        fth_status st0 = spectral_transform(M_in, sr, sm, map_store, &M_map);
+        if (st0 != FTH_OK) return st0;
+        M = &M_map;
+    }
+    fth_gle gle_map;
+    std::vector<double> gle_a, gle_c;
+    const fth_gle* gle = gle_in;
+    if (ga != 1.0 || gg != 1.0) {
+        fth_status st0 = scaled_gle(gle_in, ga, gg, gle_a, gle_c, &gle_map);
+        if (st0 != FTH_OK) return st0;
+        gle = &gle_map;
+    }
     if (opt.precision < FTH_FP64 || opt.precision > FTH_FP32_BF16X3) return fail(FTH_EINVAL, "unknown precision");
     if (opt.block_len < 1) return fail(FTH_EINVAL, "block_len must be >= 1");
     if (opt.burn_in < 0) return fail(FTH_EINVAL, "burn_in must be >= 0");

@@ -140,6 +140,11 @@ fth_status fail(fth_status st, const char* fmt, ...);
 extern thread_local std::string g_last_error;
 
 fth_status check_csr(const fth_matrix* M);
+// M' = r M + m I into store (FP64 values; the CSR pattern is shared with M).
+fth_status spectral_transform(const fth_matrix* M, double r, double m, std::vector<double>& store, fth_matrix* out);
+// A' = alpha A_p, C' = gamma C_p into A, C.
+fth_status scaled_gle(const fth_gle* g, double alpha, double gamma, std::vector<double>& A, std::vector<double>& C,
+                      fth_gle* out);
 fth_status check_dense(const fth_matrix* M);
 fth_status make_propagator(const fth_gle* g, double dt, std::vector<double>& T, std::vector<double>& S);
 // Allocate (and zero) the state for R replicas; fixes R and the launch shape.

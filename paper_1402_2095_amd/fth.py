@@ -29,7 +29,9 @@ EXPORTS = [
     "fth_destroy", "fth_last_error", "fth_version", "fth_noise_sample", "fth_force",
     "fth_server_create", "fth_server_submit", "fth_server_tick", "fth_server_poll", "fth_server_result",
     "fth_server_cancel", "fth_server_clock", "fth_server_stats", "fth_server_destroy",
+    "fth_spectral_map", "fth_gershgorin", "fth_unscale",
 ]
+FTH_TARGET_INVSQRT, FTH_TARGET_LN, FTH_TARGET_EXPNEG = 0, 1, 2
 FTH_REQ_QUEUED, FTH_REQ_RUNNING, FTH_REQ_DONE, FTH_REQ_FAILED, FTH_REQ_CANCELLED = 0, 1, 2, 3, 4
 
 
@@ -55,7 +57,9 @@ class fth_options(ctypes.Structure):
                 ("replicas", ctypes.c_int32), ("hip_stream", ctypes.c_void_p),
                 ("steps_per_graph", ctypes.c_int32), ("tune", ctypes.c_int32),
                 ("temporal_steps", ctypes.c_int32), ("temporal_threads", ctypes.c_int32),
-                ("coded_matrix", ctypes.c_int32), ("acc_pp", ctypes.c_int32), ("acc_trace", ctypes.c_int32)]
+                ("coded_matrix", ctypes.c_int32), ("acc_pp", ctypes.c_int32), ("acc_trace", ctypes.c_int32),
+                ("scale_r", ctypes.c_double), ("scale_m", ctypes.c_double), ("gle_alpha", ctypes.c_double),
+                ("gle_gamma", ctypes.c_double)]
 
 
 class fth_server_options(ctypes.Structure):
@@ -116,6 +120,9 @@ def lib():
             "fth_server_clock": (dbl, [P]),
             "fth_server_stats": (i32, [P, P, P, P]),
             "fth_server_destroy": (i32, [P]),
+            "fth_spectral_map": (i32, [dbl, dbl, dbl, dbl, P, P]),
+            "fth_gershgorin": (i32, [P, P, P]),
+            "fth_unscale": (i32, [i32, dbl, dbl, dbl, dbl, i64, P, P, P]),
         }
         for name, (res, args) in sig.items():
             f = getattr(L, name)
@@ -280,6 +287,30 @@ def _check_plain(st: int):
         raise FthError(st, "fth_noise_sample failed")
 
 
+def fth_spectral_map(e_min: float, e_max: float, w_min: float, w_max: float):
+    r, m = ctypes.c_double(), ctypes.c_double()
+    _check(lib().fth_spectral_map(e_min, e_max, w_min, w_max, ctypes.byref(r), ctypes.byref(m)))
+    return r.value, m.value
+
+
+def fth_gershgorin(M):
+    mat = _Matrix(M)
+    lo, hi = ctypes.c_double(), ctypes.c_double()
+    _check(lib().fth_gershgorin(ctypes.byref(mat.struct), ctypes.byref(lo), ctypes.byref(hi)))
+    return lo.value, hi.value
+
+
+def fth_unscale(target: int, r: float, m: float, alpha: float, gamma: float, kind_weight, est, se=None):
+    """In-place map of position-form estimates of the transformed problem back
+    to f(M); returns (est, se) as new float64 arrays."""
+    w = np.ascontiguousarray(kind_weight, dtype=np.float64)
+    e = np.array(est, dtype=np.float64)
+    s = None if se is None else np.array(se, dtype=np.float64)
+    _check(lib().fth_unscale(int(target), float(r), float(m), float(alpha), float(gamma), len(e), _p(w), _p(e),
+                             _p(s) if s is not None else None))
+    return e, s
+
+
 def fth_destroy(ctx):
     if ctx:
         _check(lib().fth_destroy(ctx))
@@ -290,7 +321,8 @@ class Solver:
 
     def __init__(self, M, A_p, C_p, dt, pairs=None, replicas=0, precision=FTH_FP32, seed=0, stream_id=0,
                  burn_in=0, block_len=100, acc_diag=False, steps_per_graph=0, hip_stream=None, tune=False,
-                 temporal_steps=0, temporal_threads=0, coded_matrix=0, acc_pp=False, acc_trace=False):
+                 temporal_steps=0, temporal_threads=0, coded_matrix=0, acc_pp=False, acc_trace=False,
+                 scale_r=1.0, scale_m=0.0, gle_alpha=1.0, gle_gamma=1.0):
         self.n = int(M.shape[0] if isinstance(M, np.ndarray) else M.n)
         self.ns = int(np.asarray(A_p).shape[0] - 1)
         self.R = int(replicas)
@@ -298,7 +330,9 @@ class Solver:
                                   block_len=block_len, acc_diag=int(acc_diag), replicas=int(replicas),
                                   steps_per_graph=steps_per_graph, tune=int(tune),
                                   temporal_steps=int(temporal_steps), temporal_threads=int(temporal_threads),
-                                  coded_matrix=int(coded_matrix), acc_pp=int(acc_pp), acc_trace=int(acc_trace))
+                                  coded_matrix=int(coded_matrix), acc_pp=int(acc_pp), acc_trace=int(acc_trace),
+                                  scale_r=float(scale_r), scale_m=float(scale_m), gle_alpha=float(gle_alpha),
+                                  gle_gamma=float(gle_gamma))
         if hip_stream is not None:
             opt.hip_stream = hip_stream
         self.ctx = fth_create(M, A_p, C_p, dt, pairs, opt)

@@ -112,3 +112,59 @@ def test_footprint_accounting():
     assert b == expect
     # the paper's count: M + (3 + S) N + 2 A reals; state bytes dominate and scale with R
     assert fth.fth_footprint_bytes(csr, 4, 16, 10, True, fth.FTH_FP32) - b == n * 8 * 4 * 12
+
+
+def test_spectral_map_sends_the_spectrum_onto_the_window():
+    """Sec. I scaling: M' = r M + m I with r e_min + m = w_min and
+    r e_max + m = w_max (the affine map is fixed by its two end points)."""
+    for e_lo, e_hi, w_lo, w_hi in ((85.0, 180.0, 1.2, 600.0), (-3.0, 3.0, 0.1, 6.1), (0.4, 199.6, 0.1, 12.1)):
+        r, m = fth.fth_spectral_map(e_lo, e_hi, w_lo, w_hi)
+        assert abs(r * e_lo + m - w_lo) < 1e-12 * max(1, abs(w_lo)) * 100
+        assert abs(r * e_hi + m - w_hi) < 1e-12 * max(1, abs(w_hi)) * 100
+    with pytest.raises(fth.FthError):
+        fth.fth_spectral_map(1.0, 1.0, 0.1, 2.0)
+
+
+def test_gershgorin_interval():
+    M = fi.banded_spd_csr(400, 3, dtype=np.float64)
+    lo, hi = fth.fth_gershgorin(M)
+    A = np.zeros((400, 400))
+    for i in range(400):
+        for k in range(M.row_ptr[i], M.row_ptr[i + 1]):
+            A[i, M.col[k]] = M.val[k]
+    off = np.sum(np.abs(A), axis=1) - np.abs(np.diag(A))
+    assert lo == pytest.approx(np.min(np.diag(A) - off), rel=1e-12)
+    assert hi == pytest.approx(np.max(np.diag(A) + off), rel=1e-12)
+    w = np.linalg.eigvalsh(A)
+    assert lo <= w.min() and w.max() <= hi
+    D = fi.m2_gerschgorin(50, 2)
+    lo2, hi2 = fth.fth_gershgorin(D.astype(np.float64))
+    w2 = np.linalg.eigvalsh(D)
+    assert lo2 <= w2.min() and w2.max() <= hi2
+
+
+def test_unscale_against_matrix_functions():
+    """The undo identities, checked on eigendecompositions: ln(M) =
+    ln(r M) - ln(r) I, M^-1/2 = sqrt(r) (r M)^-1/2, exp(-r M) = e^m exp(-(r M + m I));
+    with (alpha, gamma) the q-response is (gamma/alpha^2) g(M'/alpha^2)."""
+    from oracle.exact import matrix_function
+    M, _ = fi.haar_spd(7, 5, 2.0, 40.0)
+    n = 7
+    iu = np.triu_indices(n)
+    w = (iu[0] == iu[1]).astype(float)
+    for target, r, m, f in ((fth.FTH_TARGET_LN, 3.0, 0.0, np.log), (fth.FTH_TARGET_INVSQRT, 0.25, 0.0, lambda x: x ** -0.5),
+                            (fth.FTH_TARGET_EXPNEG, 0.05, 1.5, lambda x: np.exp(-x))):
+        for alpha, gamma in ((1.0, 1.0), (2.0, 0.5)):
+            Mp = r * M + m * np.eye(n)
+            # what the transformed run estimates: (gamma / alpha^2) f(M' / alpha^2)
+            run = (gamma / alpha ** 2) * matrix_function(Mp / alpha ** 2, f)[iu]
+            est, se = fth.fth_unscale(target, r, m, alpha, gamma, w, run, np.ones(len(w)))
+            rr = r / alpha ** 2
+            if target == fth.FTH_TARGET_EXPNEG:   # recovers exp(-r' M), r' = r / alpha^2
+                want = matrix_function(rr * M, lambda x: np.exp(-x))[iu]
+            else:
+                want = matrix_function(M, f)[iu]
+            assert np.allclose(est, want, rtol=1e-10, atol=1e-12), (target, alpha, gamma)
+            assert np.all(se > 0)
+    with pytest.raises(fth.FthError):   # ln needs m = 0
+        fth.fth_unscale(fth.FTH_TARGET_LN, 2.0, 1.0, 1.0, 1.0, w, np.ones(len(w)))
