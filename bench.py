@@ -43,6 +43,10 @@ KERNEL_SOURCES = {
 }
 
 
+# Extra solver options of a workload (spectral map, estimators), set by workload().
+EXTRA = {}
+
+
 def workload(name: str):
     """Returns (description dict, matrix CSR, GLE, dt, R, pairs, precision, default steps)."""
     from paper_1402_2095_amd import fth
@@ -77,6 +81,32 @@ def workload(name: str):
                 "gle": "ns=4, x^-1/2 target", "replicas": 128, "estimates": "diagonal + 1024 pairs",
                 "steps_in_config": 2000}
         return desc, M, g, h, 128, pairs, prec, 2000
+    if name == "m1-logdet":
+        # the paper's M1 (logarithm example): periodic 24^3 lattice, on-site 100, hopping U[0, 2]
+        # to the first six neighbour shells (81 entries per row); log det M = Tr ln M from the
+        # position trace with the ln GLE, run on M' = r M (the spectral map of Sec. I)
+        M = fi.m1_lattice_csr(24, 6006, dtype=np.float32)
+        g = fi.load_gle("ln_ns4")
+        lo_w, hi_w = g.meta["window_lambda"]
+        _, hi = fth.fth_gershgorin(M)
+        EXTRA.update(scale_r=hi_w / hi, acc_trace=True)
+        desc = {"workload": "M1 lattice 24^3 (N=13824, 81 nonzeros/row, CSR), log det via Tr ln",
+                "gle": "ns=4, ln target, M' = r M", "replicas": 32, "estimates": "diagonal + 1024 pairs + traces",
+                "steps_in_config": 20000}
+        return desc, M, g, 0.1 / np.sqrt(hi_w), 32, fi.random_pairs(M.n, 1024, 6007), fth.FTH_FP32, 20000
+    if name == "m2-exp":
+        # the paper's M2 (exponential example): dense, eigenvalues in (-300, 300) by Gerschgorin;
+        # Tr exp(-M / 100) with the exp(-x) GLE on M' = M / 100 + 3.1 I
+        n = 2048
+        M = fi.m2_gerschgorin(n, 7007).astype(np.float32)
+        g = fi.load_gle("expneg_ns4")
+        lo_w, hi_w = g.meta["window_lambda"]
+        r, m = fth.fth_spectral_map(-300.0, 300.0, lo_w, hi_w)
+        EXTRA.update(scale_r=r, scale_m=m, acc_trace=True)
+        desc = {"workload": "M2 dense N=2048, eigenvalues in (-300, 300), Tr exp(-M/100)",
+                "gle": "ns=4, exp(-x) target, M' = M/100 + 3.1 I", "replicas": 128,
+                "estimates": "diagonal + 1024 pairs + traces", "steps_in_config": 5000}
+        return desc, M, g, 0.1 / np.sqrt(hi_w), 128, fi.random_pairs(n, 1024, 7008), fth.FTH_FP32_BF16X3, 5000
     raise SystemExit(f"unknown workload {name}")
 
 
@@ -88,6 +118,8 @@ def dense_roofline(M, ns: int, R: int, npairs: int, prec: int, per_step_s: float
     from paper_1402_2095_amd import fth
     n = M.shape[0]
     P = (n + 255) // 256 * 256
+    if P >= 2048:   # the library pads to whole 64-wide k-steps in each of its 8 K slices
+        P = (n + 511) // 512 * 512
     ks = 8 if P >= 2048 else P // 256
     b = 8 if prec == fth.FTH_FP64 else 4
     mbytes = P * P * (8 if prec == fth.FTH_FP64 else 4)
@@ -272,11 +304,15 @@ def profile_summary(d: str, workload_name: str) -> str:
 def cpu_baseline(M, g, h, R, pairs, budget_s: float):
     import oracle
     nthreads = oracle.max_threads()
+    r, m = EXTRA.get("scale_r", 1.0), EXTRA.get("scale_m", 0.0)   # the same spectral map as the GPU run
     if isinstance(M, np.ndarray):
-        M64 = M.astype(np.float64)
+        M64 = r * M.astype(np.float64) + m * np.eye(M.shape[0])
         n = M.shape[0]
     else:
-        M64 = fi.CSR(M.n, M.row_ptr, M.col, M.val.astype(np.float64))
+        val = r * M.val.astype(np.float64)
+        rows = np.repeat(np.arange(M.n), np.diff(M.row_ptr))
+        val[rows == M.col] += m
+        M64 = fi.CSR(M.n, M.row_ptr, M.col, val)
         n = M.n
     run = oracle.OracleRun(M64, g.A_p, g.C_p, h, R, np.concatenate([pairs, fi.diag_pairs(n)]), seed=2)
     run.run(1)  # warm-up
@@ -448,7 +484,7 @@ def main():
     stream = torch.cuda.current_stream()
     sol = fth.Solver(M, g.A_p, g.C_p, h, pairs=pairs, replicas=R, precision=prec, seed=2, acc_diag=True,
                      steps_per_graph=args.steps_per_graph, block_len=100, hip_stream=stream.cuda_stream,
-                     tune=not args.no_tune)
+                     tune=not args.no_tune, **EXTRA)
     if args.warmup:
         sol.run(args.warmup)
     torch.cuda.synchronize()
@@ -461,6 +497,14 @@ def main():
     assert np.all(np.isfinite(est)), "non-finite estimates"
     dense = isinstance(M, np.ndarray)
     n = M.shape[0] if dense else M.n
+    result = None
+    if args.workload in ("m1-logdet", "m2-exp"):  # the trace, mapped back to the original matrix
+        tgt = fth.FTH_TARGET_LN if args.workload == "m1-logdet" else fth.FTH_TARGET_EXPNEG
+        k = len(est) - 2          # position trace (then q^T M q)
+        e_u, s_u = fth.fth_unscale(tgt, EXTRA.get("scale_r", 1.0), EXTRA.get("scale_m", 0.0), 1.0, 1.0,
+                                   [float(n)], est[k:k + 1], se[k:k + 1])
+        result = {"quantity": "log det M" if tgt == fth.FTH_TARGET_LN else "Tr exp(-M/100)",
+                  "estimate": float(e_u[0]), "stderr": float(s_u[0]), "steps": steps + args.warmup}
     kind, unit_kernels, unit_steps = unit_of(sol.kernel_name)
     units = steps / unit_steps
     per_unit_s = gpu_ms * 1e-3 / units   # HIP events around the timed run, on the library's stream
@@ -514,6 +558,8 @@ def main():
         "roofline": roof,
         "cpu_baseline": None,
     }
+    if result is not None:
+        out["result"] = result
     if not args.no_cpu_baseline:
         out["cpu_baseline"] = cpu_baseline(M, g, h, R, pairs, args.cpu_budget)
     sol.close()

@@ -272,11 +272,18 @@ fth_status upload_TS(fth_ctx* c) {
     return FTH_OK;
 }
 
-// Dense M padded to rows_pad x rows_pad with zeros (rows_pad a multiple of
-// 256): bf16 hi/lo split on the device for the split form, FP64 as is.
+// Padded size of a dense M: a multiple of 256, and of 512 from 2048 on, where
+// the split-K GEMM cuts K into 8 slices that must each be whole 64-wide k-steps.
+int64_t dense_rows_pad(int64_t n) {
+    const int64_t p = (n + 255) / 256 * 256;
+    return p >= 2048 ? (n + 511) / 512 * 512 : p;
+}
+
+// Dense M padded to rows_pad x rows_pad with zeros: bf16 hi/lo split on the
+// device for the split form, FP64 as is.
 fth_status upload_dense(fth_ctx* c, const std::vector<double>& M) {
     const int64_t n = c->n;
-    c->rows_pad = (n + 255) / 256 * 256;
+    c->rows_pad = dense_rows_pad(n);
     const int64_t P = c->rows_pad;
     c->ksplit = P >= 2048 ? 8 : int(P / 256);
     const size_t cnt = size_t(P) * size_t(P);
@@ -913,7 +920,7 @@ size_t fth_footprint_bytes(const fth_matrix* M, int32_t ns, int32_t R, int64_t n
         bytes += (n + 1) * 8 + size_t(M->nnz) * (4 + rb);
         bytes += n * size_t(R) * rb * 2 + 2 * ps_rows * size_t(R) * rb * size_t(1 + ns);
     } else {
-        const size_t P = (n + 255) / 256 * 256;
+        const size_t P = size_t(dense_rows_pad(int64_t(n)));
         const size_t ks = P >= 2048 ? 8 : P / 256;
         bytes += P * P * (precision == FTH_FP32_BF16X3 ? 4 : rb);           // M (hi + lo, or FP64)
         bytes += 2 * P * size_t(R) * rb + 2 * ps_rows * size_t(R) * rb * size_t(1 + ns);  // q, (p, s) pairs

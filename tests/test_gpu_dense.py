@@ -28,7 +28,8 @@ def dense_case(n, seed=4004):
 
 
 @pytest.mark.parametrize("prec", [fth.FTH_FP64, fth.FTH_FP32_BF16X3], ids=["fp64", "bf16x3"])
-@pytest.mark.parametrize("n,R", [(300, 16), (1000, 32), (520, 128)])
+# 2195 pads to 2560: eight K slices of 320 (whole 64-wide k-steps)
+@pytest.mark.parametrize("n,R", [(300, 16), (1000, 32), (520, 128), (2195, 64)])
 def test_force_against_fp64_gemm(prec, n, R):
     M, h = dense_case(n)
     g = fi.load_gle("invsqrt_ns4")
