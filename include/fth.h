@@ -109,6 +109,15 @@ typedef struct {
     const double* C_p;
 } fth_gle;
 
+/* Device memory provider (e.g. a framework's caching allocator).  alloc
+ * returns device memory of at least `bytes` (NULL on failure); release gives
+ * it back.  Both are called from the thread that calls into the library. */
+typedef struct {
+    void* (*alloc)(size_t bytes, void* user);
+    void (*release)(void* ptr, void* user);
+    void* user;
+} fth_allocator;
+
 typedef struct {
     uint64_t seed;           /* Philox key */
     uint32_t stream_id;      /* Philox counter word 3 (distinct per request) */
@@ -151,6 +160,9 @@ typedef struct {
     double scale_m;
     double gle_alpha;
     double gle_gamma;
+    const fth_allocator* allocator; /* NULL: hipMalloc / hipFree; else every device buffer of
+                                       the context (and its scratch) comes from it; copied at
+                                       create, the functions must stay valid until destroy */
 } fth_options;
 
 /* Fill *opt with defaults: seed 0, stream 0, FTH_FP32, burn_in 0,
@@ -267,6 +279,19 @@ typedef enum {
  * or a map the target cannot undo. */
 fth_status fth_unscale(int32_t target, double r, double m, double alpha, double gamma, int64_t count,
                        const double* kind_weight, double* est, double* se);
+
+/* Device bytes the context holds now (all its buffers, through the allocator). */
+size_t fth_device_bytes(const fth_ctx* ctx);
+
+/* Complete state of a solve (q, p, s, accumulators, step counter; the noise
+ * is counter-based, so this is all a continuation needs) as a byte image.
+ * With buf == NULL, *len receives the size; else len must be at least that.
+ * fth_load restores an image into a context created with the same matrix
+ * size, GLE size, precision, replicas, outputs, seed and stream id: the
+ * continuation is bit-identical to the uninterrupted run.  FTH_EINVAL on a
+ * size or parameter mismatch or a damaged image. */
+fth_status fth_save(fth_ctx* ctx, void* buf, size_t* len);
+fth_status fth_load(fth_ctx* ctx, const void* buf, size_t len);
 
 /* Device bytes a context with these parameters allocates. */
 size_t fth_footprint_bytes(const fth_matrix* M, int32_t ns, int32_t replicas,

@@ -296,9 +296,9 @@ fth_status upload_dense(fth_ctx* c, const std::vector<double>& M) {
     }
     if (c->prec != FTH_FP32_BF16X3)
         return fail(FTH_EUNSUPPORTED, "dense systems beyond one workgroup use FTH_FP32_BF16X3 or FTH_FP64");
-    float* tmp = nullptr;
-    HIP_OK(hipMalloc(&tmp, cnt * sizeof(float)));
-    std::unique_ptr<float, hipError_t (*)(void*)> guard(tmp, hipFree);
+    ctx_scratch scratch(c);
+    float* tmp = static_cast<float*>(scratch.get(cnt * sizeof(float)));
+    if (!tmp) return fail(FTH_ENOMEM, "scratch allocation for the bf16 split failed");
     HIP_OK(hipMemset(tmp, 0, cnt * sizeof(float)));
     {
         std::vector<float> mf(size_t(n) * size_t(n));
@@ -764,17 +764,14 @@ fth_status autotune(fth_ctx* c) {
     const size_t qb = size_t(c->q_rows()) * size_t(c->R) * rb;
     const size_t psb = c->ps_bytes();
     const size_t ab = sizeof(double) * size_t(3 * c->n_out());
-    struct Saved {
-        std::vector<void*> p;
-        ~Saved() { for (void* x : p) (void)hipFree(x); }
-    } sv;
+    ctx_scratch sv(c);
     void* bufs[4] = {c->d_q[0], c->d_q[1], c->d_ps[c->step & 1], c->d_acc};
     const size_t sizes[4] = {qb, qb, psb, std::max<size_t>(ab, 8)};
+    void* saved[4];
     for (int k = 0; k < 4; ++k) {
-        void* x = nullptr;
-        HIP_OK(hipMalloc(&x, sizes[k]));
-        sv.p.push_back(x);
-        HIP_OK(hipMemcpyAsync(x, bufs[k], sizes[k], hipMemcpyDeviceToDevice, c->stream));
+        saved[k] = sv.get(sizes[k]);
+        if (!saved[k]) return fail(FTH_ENOMEM, "autotuner could not save the state");
+        HIP_OK(hipMemcpyAsync(saved[k], bufs[k], sizes[k], hipMemcpyDeviceToDevice, c->stream));
     }
     int64_t step0 = 0;
     HIP_OK(hipMemcpy(&step0, c->d_step, sizeof(int64_t), hipMemcpyDeviceToHost));
@@ -816,7 +813,7 @@ fth_status autotune(fth_ctx* c) {
         c->tb_kt = 0;
     }
     // restore
-    for (int k = 0; k < 4; ++k) HIP_OK(hipMemcpyAsync(bufs[k], sv.p[k], sizes[k], hipMemcpyDeviceToDevice, c->stream));
+    for (int k = 0; k < 4; ++k) HIP_OK(hipMemcpyAsync(bufs[k], saved[k], sizes[k], hipMemcpyDeviceToDevice, c->stream));
     HIP_OK(hipMemcpyAsync(c->d_step, &step0, sizeof(int64_t), hipMemcpyHostToDevice, c->stream));
     HIP_OK(hipMemsetAsync(c->d_flag, 0, sizeof(int32_t), c->stream));
     HIP_OK(hipStreamSynchronize(c->stream));
@@ -986,6 +983,11 @@ fth_status fth_create(const fth_matrix* M_in, const fth_gle* gle_in, double dt, 
     if (gle && (gle->ns > fth::kNsMax)) return fail(FTH_EUNSUPPORTED, "ns > %d not instantiated", fth::kNsMax);
 
     std::unique_ptr<fth_ctx> c(new fth_ctx());
+    if (opt.allocator) {
+        if (!opt.allocator->alloc || !opt.allocator->release)
+            return fail(FTH_EINVAL, "an allocator needs both alloc and release");
+        c->hook = *opt.allocator;
+    }
     c->n = M->n;
     c->fmt = M->format;
     c->prec = opt.precision;
@@ -1223,16 +1225,8 @@ fth_status fth_force(fth_ctx* c, const double* q, double* F) {
     HIP_OK(hipStreamSynchronize(c->stream));
     const int64_t P = c->rows_pad, R = c->R, n = c->n;
     const size_t rb = c->real_bytes();
-    struct Tmp {
-        std::vector<void*> p;
-        ~Tmp() { for (void* x : p) (void)hipFree(x); }
-    } tmp;
-    auto alloc = [&](size_t b) -> void* {
-        void* x = nullptr;
-        if (hipMalloc(&x, b) != hipSuccess) return nullptr;
-        tmp.p.push_back(x);
-        return x;
-    };
+    ctx_scratch tmp(c);
+    auto alloc = [&](size_t b) -> void* { return tmp.get(b); };
     void* dq = alloc(size_t(P * R) * rb);
     void* dpart = alloc(size_t(c->ksplit) * size_t(P * R) * rb);
     int64_t* dstep = static_cast<int64_t*>(alloc(sizeof(int64_t)));
@@ -1303,6 +1297,108 @@ fth_status fth_kernel_name(const fth_ctx* c, char* name, size_t len) {
         std::snprintf(name, len, "csr_step_kernel<%s,NS=%d,RPT=%d,NT=%d,CODED=%d> block=%d%s",
                       c->prec == FTH_FP64 ? "double" : "float", c->ns, c->rpt, int(c->nt),
                       int(c->coded && c->rpt >= 4), c->block, c->tuned ? " (autotuned)" : "");
+    return FTH_OK;
+}
+
+size_t fth_device_bytes(const fth_ctx* c) { return c ? c->device_bytes() : 0; }
+
+namespace {
+struct SaveHeader {
+    char magic[8];
+    uint32_t version, prec;
+    int64_t n, R, ns, n_out, step, q_bytes, ps_bytes;
+    uint64_t seed;
+    uint32_t stream_id, poisoned;
+};
+constexpr char kSaveMagic[8] = {'F', 'T', 'H', 'S', 'T', 'A', 'T', 'E'};
+
+uint64_t fnv1a(const unsigned char* p, size_t n) {
+    uint64_t h = 1469598103934665603ull;
+    for (size_t k = 0; k < n; ++k) h = (h ^ p[k]) * 1099511628211ull;
+    return h;
+}
+
+size_t image_bytes(const fth_ctx* c) {
+    return sizeof(SaveHeader) + size_t(c->q_rows()) * size_t(c->R) * c->real_bytes() + c->ps_bytes() +
+           sizeof(double) * 3 * size_t(c->n_out()) + sizeof(uint64_t);
+}
+}  // namespace
+
+fth_status fth_save(fth_ctx* c, void* buf, size_t* len) {
+    if (!c || !len) return fail(FTH_EINVAL, "invalid arguments");
+    if (c->R == 0) return fail(FTH_ESTATE, "state not allocated (replica count not fixed)");
+    const size_t need = image_bytes(c);
+    if (!buf) {
+        *len = need;
+        return FTH_OK;
+    }
+    if (*len < need) return fail(FTH_EINVAL, "buffer too small (%zu < %zu bytes)", *len, need);
+    HIP_OK(hipStreamSynchronize(c->stream));
+    SaveHeader hd{};
+    std::memcpy(hd.magic, kSaveMagic, 8);
+    hd.version = 1;
+    hd.prec = uint32_t(c->prec);
+    hd.n = c->n;
+    hd.R = c->R;
+    hd.ns = c->ns;
+    hd.n_out = c->n_out();
+    hd.step = c->step;
+    hd.q_bytes = int64_t(size_t(c->q_rows()) * size_t(c->R) * c->real_bytes());
+    hd.ps_bytes = int64_t(c->ps_bytes());
+    hd.seed = c->opt.seed;
+    hd.stream_id = c->opt.stream_id;
+    hd.poisoned = c->poisoned ? 1u : 0u;
+    unsigned char* out = static_cast<unsigned char*>(buf);
+    std::memcpy(out, &hd, sizeof(hd));
+    size_t off = sizeof(hd);
+    HIP_OK(hipMemcpy(out + off, c->d_q[c->step & 1], size_t(hd.q_bytes), hipMemcpyDeviceToHost));
+    off += size_t(hd.q_bytes);
+    HIP_OK(hipMemcpy(out + off, c->d_ps[c->step & 1], size_t(hd.ps_bytes), hipMemcpyDeviceToHost));
+    off += size_t(hd.ps_bytes);
+    const size_t ab = sizeof(double) * 3 * size_t(hd.n_out);
+    if (ab) HIP_OK(hipMemcpy(out + off, c->d_acc, ab, hipMemcpyDeviceToHost));
+    off += ab;
+    const uint64_t sum = fnv1a(out, off);
+    std::memcpy(out + off, &sum, sizeof(sum));
+    *len = need;
+    return FTH_OK;
+}
+
+fth_status fth_load(fth_ctx* c, const void* buf, size_t len) {
+    if (!c || !buf) return fail(FTH_EINVAL, "invalid arguments");
+    if (len < sizeof(SaveHeader) + sizeof(uint64_t)) return fail(FTH_EINVAL, "image too short");
+    SaveHeader hd;
+    std::memcpy(&hd, buf, sizeof(hd));
+    if (std::memcmp(hd.magic, kSaveMagic, 8) != 0 || hd.version != 1) return fail(FTH_EINVAL, "not a state image");
+    if (hd.R < 1 || hd.R > 512) return fail(FTH_EINVAL, "damaged image (replicas)");
+    fth_status st = ensure_state(c, int32_t(hd.R));
+    if (st != FTH_OK) return st;
+    if (image_bytes(c) != len) return fail(FTH_EINVAL, "image size %zu does not match this context (%zu)", len, image_bytes(c));
+    if (hd.prec != uint32_t(c->prec) || hd.n != c->n || hd.ns != c->ns || hd.n_out != c->n_out() ||
+        hd.q_bytes != int64_t(size_t(c->q_rows()) * size_t(c->R) * c->real_bytes()) ||
+        hd.ps_bytes != int64_t(c->ps_bytes()))
+        return fail(FTH_EINVAL, "image was saved from a context of another shape");
+    if (hd.seed != c->opt.seed || hd.stream_id != c->opt.stream_id)
+        return fail(FTH_EINVAL, "image was saved with another noise stream (seed or stream id)");
+    if (hd.step < 0 || hd.step >= (int64_t(1) << 32)) return fail(FTH_EINVAL, "damaged image (step)");
+    const unsigned char* in = static_cast<const unsigned char*>(buf);
+    uint64_t sum;
+    std::memcpy(&sum, in + len - sizeof(sum), sizeof(sum));
+    if (fnv1a(in, len - sizeof(sum)) != sum) return fail(FTH_EINVAL, "image checksum mismatch");
+    HIP_OK(hipStreamSynchronize(c->stream));
+    c->step = hd.step;
+    size_t off = sizeof(hd);
+    HIP_OK(hipMemcpy(c->d_q[c->step & 1], in + off, size_t(hd.q_bytes), hipMemcpyHostToDevice));
+    off += size_t(hd.q_bytes);
+    HIP_OK(hipMemcpy(c->d_ps[c->step & 1], in + off, size_t(hd.ps_bytes), hipMemcpyHostToDevice));
+    off += size_t(hd.ps_bytes);
+    const size_t ab = sizeof(double) * 3 * size_t(hd.n_out);
+    if (ab) HIP_OK(hipMemcpy(c->d_acc, in + off, ab, hipMemcpyHostToDevice));
+    HIP_OK(hipMemcpy(c->d_step, &c->step, sizeof(int64_t), hipMemcpyHostToDevice));
+    const int32_t flag = hd.poisoned ? 1 : 0;
+    HIP_OK(hipMemcpy(c->d_flag, &flag, sizeof(flag), hipMemcpyHostToDevice));
+    c->poisoned = hd.poisoned != 0;
+    c->qt_dirty = true;
     return FTH_OK;
 }
 

@@ -89,13 +89,36 @@ struct fth_ctx {
     double last_ms = 0.0;
     int device = 0;
 
+    fth_allocator hook{};      // caller's device allocator (alloc == NULL: hipMalloc / hipFree)
+    std::vector<size_t> alloc_bytes;  // sizes of allocs, same order
+
     ~fth_ctx() {
         if (gexec) (void)hipGraphExecDestroy(gexec);
         if (ev0) (void)hipEventDestroy(ev0);
         if (ev1) (void)hipEventDestroy(ev1);
         if (stream) (void)hipStreamSynchronize(stream);
-        for (void* p : allocs) (void)hipFree(p);
+        for (void* p : allocs) raw_free(p);
         if (stream) (void)hipStreamDestroy(stream);
+    }
+
+    // Device memory through the caller's allocator when one is given.
+    void* raw_alloc(size_t bytes) {
+        if (hook.alloc) return hook.alloc(bytes, hook.user);
+        void* p = nullptr;
+        return hipMalloc(&p, bytes) == hipSuccess ? p : nullptr;
+    }
+    void raw_free(void* p) {
+        if (!p) return;
+        if (hook.alloc) {
+            if (hook.release) hook.release(p, hook.user);
+        } else {
+            (void)hipFree(p);
+        }
+    }
+    size_t device_bytes() const {
+        size_t s = 0;
+        for (size_t b : alloc_bytes) s += b;
+        return s;
     }
 
     size_t real_bytes() const { return prec == FTH_FP64 ? 8 : 4; }
@@ -115,21 +138,38 @@ struct fth_ctx {
     }
 
     void dfree(void*& p) {
-        for (auto it = allocs.begin(); it != allocs.end(); ++it)
-            if (*it == p) {
-                allocs.erase(it);
-                (void)hipFree(p);
+        for (size_t k = 0; k < allocs.size(); ++k)
+            if (allocs[k] == p) {
+                allocs.erase(allocs.begin() + long(k));
+                alloc_bytes.erase(alloc_bytes.begin() + long(k));
+                raw_free(p);
                 break;
             }
         p = nullptr;
     }
 
     hipError_t dalloc(void** p, size_t bytes) {
-        *p = nullptr;
         if (bytes == 0) bytes = 256;
-        hipError_t e = hipMalloc(p, bytes);
-        if (e == hipSuccess) allocs.push_back(*p);
-        return e;
+        *p = raw_alloc(bytes);
+        if (!*p) return hipErrorOutOfMemory;
+        allocs.push_back(*p);
+        alloc_bytes.push_back(bytes);
+        return hipSuccess;
+    }
+};
+
+// Scratch device memory for the duration of one call (freed on scope exit).
+struct ctx_scratch {
+    fth_ctx* c;
+    std::vector<void*> p;
+    explicit ctx_scratch(fth_ctx* ctx) : c(ctx) {}
+    ~ctx_scratch() {
+        for (void* x : p) c->raw_free(x);
+    }
+    void* get(size_t bytes) {
+        void* x = c->raw_alloc(bytes);
+        if (x) p.push_back(x);
+        return x;
     }
 };
 

@@ -29,7 +29,7 @@ EXPORTS = [
     "fth_destroy", "fth_last_error", "fth_version", "fth_noise_sample", "fth_force",
     "fth_server_create", "fth_server_submit", "fth_server_tick", "fth_server_poll", "fth_server_result",
     "fth_server_cancel", "fth_server_clock", "fth_server_stats", "fth_server_destroy",
-    "fth_spectral_map", "fth_gershgorin", "fth_unscale",
+    "fth_spectral_map", "fth_gershgorin", "fth_unscale", "fth_device_bytes", "fth_save", "fth_load",
 ]
 FTH_TARGET_INVSQRT, FTH_TARGET_LN, FTH_TARGET_EXPNEG = 0, 1, 2
 FTH_REQ_QUEUED, FTH_REQ_RUNNING, FTH_REQ_DONE, FTH_REQ_FAILED, FTH_REQ_CANCELLED = 0, 1, 2, 3, 4
@@ -59,7 +59,34 @@ class fth_options(ctypes.Structure):
                 ("temporal_steps", ctypes.c_int32), ("temporal_threads", ctypes.c_int32),
                 ("coded_matrix", ctypes.c_int32), ("acc_pp", ctypes.c_int32), ("acc_trace", ctypes.c_int32),
                 ("scale_r", ctypes.c_double), ("scale_m", ctypes.c_double), ("gle_alpha", ctypes.c_double),
-                ("gle_gamma", ctypes.c_double)]
+                ("gle_gamma", ctypes.c_double), ("allocator", ctypes.c_void_p)]
+
+
+ALLOC_FN = ctypes.CFUNCTYPE(ctypes.c_void_p, ctypes.c_size_t, ctypes.c_void_p)
+RELEASE_FN = ctypes.CFUNCTYPE(None, ctypes.c_void_p, ctypes.c_void_p)
+
+
+class fth_allocator(ctypes.Structure):
+    _fields_ = [("alloc", ALLOC_FN), ("release", RELEASE_FN), ("user", ctypes.c_void_p)]
+
+
+def torch_allocator():
+    """An fth_allocator that takes device memory from PyTorch's caching
+    allocator (the struct and its callbacks must be kept alive while a
+    context uses them)."""
+    import torch
+
+    def _alloc(nbytes, _user):
+        try:
+            return int(torch.cuda.caching_allocator_alloc(int(nbytes)))
+        except RuntimeError:
+            return None
+
+    def _release(ptr, _user):
+        torch.cuda.caching_allocator_delete(int(ptr))
+
+    a = fth_allocator(ALLOC_FN(_alloc), RELEASE_FN(_release), None)
+    return a
 
 
 class fth_server_options(ctypes.Structure):
@@ -123,6 +150,9 @@ def lib():
             "fth_spectral_map": (i32, [dbl, dbl, dbl, dbl, P, P]),
             "fth_gershgorin": (i32, [P, P, P]),
             "fth_unscale": (i32, [i32, dbl, dbl, dbl, dbl, i64, P, P, P]),
+            "fth_device_bytes": (ctypes.c_size_t, [P]),
+            "fth_save": (i32, [P, P, P]),
+            "fth_load": (i32, [P, P, ctypes.c_size_t]),
         }
         for name, (res, args) in sig.items():
             f = getattr(L, name)
@@ -311,6 +341,23 @@ def fth_unscale(target: int, r: float, m: float, alpha: float, gamma: float, kin
     return e, s
 
 
+def fth_device_bytes(ctx) -> int:
+    return int(lib().fth_device_bytes(ctx))
+
+
+def fth_save(ctx) -> bytes:
+    n = ctypes.c_size_t()
+    _check(lib().fth_save(ctx, None, ctypes.byref(n)))
+    buf = ctypes.create_string_buffer(n.value)
+    _check(lib().fth_save(ctx, buf, ctypes.byref(n)))
+    return buf.raw[:n.value]
+
+
+def fth_load(ctx, image: bytes):
+    buf = ctypes.create_string_buffer(image, len(image))
+    _check(lib().fth_load(ctx, buf, len(image)))
+
+
 def fth_destroy(ctx):
     if ctx:
         _check(lib().fth_destroy(ctx))
@@ -322,7 +369,7 @@ class Solver:
     def __init__(self, M, A_p, C_p, dt, pairs=None, replicas=0, precision=FTH_FP32, seed=0, stream_id=0,
                  burn_in=0, block_len=100, acc_diag=False, steps_per_graph=0, hip_stream=None, tune=False,
                  temporal_steps=0, temporal_threads=0, coded_matrix=0, acc_pp=False, acc_trace=False,
-                 scale_r=1.0, scale_m=0.0, gle_alpha=1.0, gle_gamma=1.0):
+                 scale_r=1.0, scale_m=0.0, gle_alpha=1.0, gle_gamma=1.0, allocator=None):
         self.n = int(M.shape[0] if isinstance(M, np.ndarray) else M.n)
         self.ns = int(np.asarray(A_p).shape[0] - 1)
         self.R = int(replicas)
@@ -335,6 +382,9 @@ class Solver:
                                   gle_gamma=float(gle_gamma))
         if hip_stream is not None:
             opt.hip_stream = hip_stream
+        self._allocator = allocator   # the library keeps calling it: hold a reference
+        if allocator is not None:
+            opt.allocator = ctypes.cast(ctypes.pointer(allocator), ctypes.c_void_p)
         self.ctx = fth_create(M, A_p, C_p, dt, pairs, opt)
 
     def run(self, nsteps, replicas=0):
@@ -357,6 +407,17 @@ class Solver:
 
     def force(self, q):
         return fth_force(self.ctx, q)
+
+    def save(self) -> bytes:
+        return fth_save(self.ctx)
+
+    def load(self, image: bytes):
+        fth_load(self.ctx, image)
+        return self
+
+    @property
+    def device_bytes(self) -> int:
+        return fth_device_bytes(self.ctx)
 
     @property
     def last_run_ms(self):
