@@ -120,3 +120,20 @@ def test_autotuner_may_block_and_keeps_trajectory():
         assert np.array_equal(x, y)
     for x, y in zip(a.accumulators()[:3], b.accumulators()[:3]):
         assert np.allclose(x, y, rtol=1e-12, atol=0)
+
+
+def test_blocked_full_size_bit_identical():
+    """Banded N = 1e6, R = 32 in the launch shape the benchmark's autotuner
+    picks (KT = 5, 1024 threads): bit-identical to the one-step kernel."""
+    g = fi.load_gle("fermi_b20_ns4")
+    M = fi.banded_spd_csr(1_000_000, 3003)
+    h = fi.dt_rule(fi.gershgorin_max(M))
+    kw = dict(pairs=fi.random_pairs(M.n, 1024, 3004), replicas=32, seed=2, acc_diag=True, block_len=4,
+              steps_per_graph=10)
+    a = fth.Solver(M, g.A_p, g.C_p, h, temporal_steps=5, temporal_threads=1024, **kw).run(20)
+    b = fth.Solver(M, g.A_p, g.C_p, h, temporal_steps=-1, **kw).run(20)
+    assert "KT=5" in a.kernel_name and "block=1024" in a.kernel_name
+    for x, y in zip(a.state(), b.state()):
+        assert np.array_equal(x, y)
+    for x, y in zip(a.accumulators()[:3], b.accumulators()[:3]):
+        assert np.array_equal(x, y)
