@@ -10,10 +10,11 @@
 // FP64 form (FTH_FP64): v_mfma_f64_16x16x4_f64 on M and q_n directly.
 //
 // Work split: the output rows are cut into row blocks and the K dimension
-// into ksplit slices; workgroup b takes K slice b mod ksplit and row block
-// b / ksplit.  The hardware deals workgroups round-robin over the 8 XCDs,
-// so with ksplit = 8 every workgroup of one K slice runs on one XCD and the
-// q_n slice it streams stays in that XCD's L2.  Each workgroup writes FP32
+// into ksplit slices (a power of two <= 8); workgroup b takes K slice
+// b mod ksplit and row block b / ksplit.  The hardware deals workgroups
+// round-robin over the 8 XCDs, so the workgroups of K slice s run on the
+// XCDs x with x mod ksplit = s, and the q_n slice they stream stays in
+// those XCDs' L2.  Each workgroup writes FP32
 // (FP64) partial sums part[ks][row][col]; the epilogue adds the ksplit
 // partials in slice order, so the result does not depend on scheduling.
 //
@@ -22,8 +23,19 @@
 //                  and D[4(l/16)+e][l%16], t < 8, e < 4.
 //   16x16x4  f64 : lane l holds A[l%16][l/16], B[l/16][l%16],
 //                  and D[4e+l/16][l%16], e < 4.
-// M is row-major, so an A fragment is 16 contiguous bytes (bf16) of one
-// row.  The bf16 B fragment needs 8 consecutive k of one column, so q_n is
+// In the split form M_hi and M_lo are kept together in a tiled layout,
+// written once by the split kernel, in which every load of a wave is 1 KB
+// of contiguous memory: for row block rb (128 rows) and k-step kb (64 k)
+// one 32 KB tile holds, per wave w and load slot u < 8, the 64 lanes'
+// 16-byte A fragments side by side,
+//     mt[((rb * rows_pad / 64 + kb) * 4 + w) * 8 + u][lane],
+// slot u carrying part (u >> 1) & 1 (0: hi, 1: lo) of row
+// 128 rb + 32 w + 16 (u >> 2) + lane % 16 at k = 64 kb + 16 (lane / 16) +
+// 8 (u & 1) + (0..7).  The k-steps of one K slice are consecutive tiles,
+// so a workgroup streams one contiguous run of memory.  (Row-major, each
+// load instruction touched 16 rows 32 KB apart and M streamed at about
+// half the rate.)  In the FP64 form M is row-major, so an A fragment is
+// 4 contiguous doubles of one row.  The bf16 B fragment needs 8 consecutive k of one column, so q_n is
 // kept as qt[k/8][col][hi|lo][k%8] (written by the epilogue): a k-step of
 // 64 is one contiguous 256*R-byte chunk, staged through LDS and shared by
 // the four waves.  The f64 B fragment is one element, so q_n [k][col] is
@@ -82,12 +94,12 @@ __device__ __forceinline__ void scatter_chunk(T* __restrict__ dst, const T (&src
 }
 
 // ------------------------------------------------------ split-BF16x3 GEMM
-// A k-step covers 64 consecutive k, so the four lane groups of a row read its
-// whole 128-byte line of M_hi (and of M_lo) at once: a line is never half
-// used and evicted before its second half is read.  Inside a k-step the k
-// order is permuted (a sum may be taken in any order): lane group g owns
-// k = 16 g + 8 t + (0..7) in substep t = 0, 1, so its A data are 32
-// contiguous bytes per row, and its B fragment is q-chunk block 2 g + t.
+// A k-step covers 64 consecutive k: one 32 KB tile of M (hi and lo parts)
+// and one 32 KB chunk of q_n, both fetched one k-step ahead.  M is read once
+// per step, so its loads are non-temporal (they do not evict q_n from L2).  Inside a
+// k-step the k order is permuted (a sum may be taken in any order): lane
+// group g owns k = 16 g + 8 t + (0..7) in substep t = 0, 1, so its B
+// fragment is q-chunk block 2 g + t.
 template <int RT>
 __global__ __launch_bounds__(256, 2) void gemm_bf16x3_kernel(const DenseGemmArgs g) {
     constexpr int R = 16 * RT;
@@ -104,15 +116,10 @@ __global__ __launch_bounds__(256, 2) void gemm_bf16x3_kernel(const DenseGemmArgs
     const int w = threadIdx.x >> 6, l = threadIdx.x & 63;
     const int lr = l & 15, lg = l >> 4;
     const int64_t P = g.rows_pad;
-    const uint16_t* mh = static_cast<const uint16_t*>(g.m_hi);
-    const uint16_t* ml = static_cast<const uint16_t*>(g.m_lo);
     const u32x4* qsrc = reinterpret_cast<const u32x4*>(g.qt);
-
-    const int64_t row0 = m0 + 32 * w + lr;  // rows row0 and row0 + 16
-    const uint16_t* a_hi0 = mh + row0 * P + 16 * lg;
-    const uint16_t* a_hi1 = a_hi0 + 16 * P;
-    const uint16_t* a_lo0 = ml + row0 * P + 16 * lg;
-    const uint16_t* a_lo1 = a_lo0 + 16 * P;
+    constexpr int TILE = 4 * 8 * 64;  // 16-byte units per (row block, k-step) tile
+    // this wave's slots of the first tile of the K slice (rows m0 + 32 w + lr and + 16)
+    const u32x4* mt = static_cast<const u32x4*>(g.m_hi) + (rb * (P / KS) + kbeg / KS) * TILE + w * (8 * 64) + l;
 
     f32x4 acc[2][RT];
 #pragma unroll
@@ -127,19 +134,19 @@ __global__ __launch_bounds__(256, 2) void gemm_bf16x3_kernel(const DenseGemmArgs
     {                                                                              \
         const int64_t kf = kbeg + int64_t(J) * KS;                                 \
         gather_chunk<u32x4, CHUNK, PER_THREAD>(rq, qsrc + (kf / 8) * R * 2);       \
-        ra[0] = *reinterpret_cast<const u32x4*>(a_hi0 + kf);                       \
-        ra[1] = *reinterpret_cast<const u32x4*>(a_hi0 + kf + 8);                   \
-        ra[2] = *reinterpret_cast<const u32x4*>(a_lo0 + kf);                       \
-        ra[3] = *reinterpret_cast<const u32x4*>(a_lo0 + kf + 8);                   \
-        ra[4] = *reinterpret_cast<const u32x4*>(a_hi1 + kf);                       \
-        ra[5] = *reinterpret_cast<const u32x4*>(a_hi1 + kf + 8);                   \
-        ra[6] = *reinterpret_cast<const u32x4*>(a_lo1 + kf);                       \
-        ra[7] = *reinterpret_cast<const u32x4*>(a_lo1 + kf + 8);                   \
+        const u32x4* src = mt + int64_t(J) * TILE;                                 \
+        _Pragma("unroll") for (int u = 0; u < 8; ++u) ra[u] = __builtin_nontemporal_load(src + u * 64); \
     }
     FTH_BF16_FETCH(0)
     for (int j = 0; j < nsteps; ++j) {
         u32x4* buf = qs[j & 1];
-        scatter_chunk<u32x4, CHUNK, PER_THREAD>(buf, rq);
+        // staged planar, [hi|lo][k/8][R], so the B reads below are 16 contiguous
+        // bytes per lane (no bank conflicts)
+#pragma unroll
+        for (int u = 0; u < PER_THREAD; ++u) {
+            const int idx = int(threadIdx.x) + 256 * u;
+            if (CHUNK % 256 == 0 || idx < CHUNK) buf[(idx & 1) * (CHUNK / 2) + (idx >> 1)] = rq[u];
+        }
         bf16x8 a[8];
 #pragma unroll
         for (int u = 0; u < 8; ++u) a[u] = __builtin_bit_cast(bf16x8, ra[u]);
@@ -149,9 +156,9 @@ __global__ __launch_bounds__(256, 2) void gemm_bf16x3_kernel(const DenseGemmArgs
         for (int t = 0; t < 2; ++t)
 #pragma unroll
             for (int c = 0; c < RT; ++c) {
-                const u32x4* bsrc = buf + ((2 * lg + t) * R + 16 * c + lr) * 2;
+                const u32x4* bsrc = buf + (2 * lg + t) * R + 16 * c + lr;
                 const bf16x8 bhi = __builtin_bit_cast(bf16x8, bsrc[0]);
-                const bf16x8 blo = __builtin_bit_cast(bf16x8, bsrc[1]);
+                const bf16x8 blo = __builtin_bit_cast(bf16x8, bsrc[CHUNK / 2]);
                 // row tile 0: a[0 + t] (hi), a[2 + t] (lo); row tile 1: a[4 + t], a[6 + t]
                 acc[0][c] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(a[0 + t], bhi, acc[0][c], 0, 0, 0);
                 acc[1][c] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(a[4 + t], bhi, acc[1][c], 0, 0, 0);
@@ -240,14 +247,16 @@ __device__ __forceinline__ void dense_row(const StepArgs<Real>& a, const StepInf
                                           Real* qw, double* trow) {
     using V = Vec<Real, RPT>;
     const int64_t R = a.R;
+    Real xi[NS + 1][RPT];
+    const bool early = noise_first();
+    if (early) row_noise<Real, NS, RPT>(a, si, i, xi);
     const RowState<Real, NS, RPT> st = load_row<Real, NS, RPT, NT>(a, si, qr, i);
     constexpr int KMAX = 8;
     V pv[KMAX];
 #pragma unroll
     for (int s = 0; s < KMAX; ++s)
         if (s < a.ksplit) pv[s] = load_state<Real, RPT, true>(a.part + (int64_t(s) * a.rows_pad + i) * R + si.r0);
-    Real xi[NS + 1][RPT];
-    row_noise<Real, NS, RPT>(a, si, i, xi);
+    if (!early) row_noise<Real, NS, RPT>(a, si, i, xi);
     Real acc[RPT];
 #pragma unroll
     for (int m = 0; m < RPT; ++m) acc[m] = Real(0);

@@ -279,13 +279,25 @@ int64_t dense_rows_pad(int64_t n) {
     return p >= 2048 ? (n + 511) / 512 * 512 : p;
 }
 
+// K slices of the dense force GEMM.  FP64: 8 from 2048 rows on.  Split form:
+// the largest power of two <= 8 that keeps the grid at or under 512
+// workgroups of 128 rows (two per CU, one round): fewer slices mean fewer
+// partial sums for the epilogue to read (16384 rows: 4 slices).
+int dense_ksplit(int64_t P, int prec) {
+    if (P < 2048) return int(P / 256);
+    int ks = 8;
+    if (prec == FTH_FP32_BF16X3)
+        while (ks > 1 && (P / 128) * ks > 512) ks /= 2;
+    return ks;
+}
+
 // Dense M padded to rows_pad x rows_pad with zeros: bf16 hi/lo split on the
 // device for the split form, FP64 as is.
 fth_status upload_dense(fth_ctx* c, const std::vector<double>& M) {
     const int64_t n = c->n;
     c->rows_pad = dense_rows_pad(n);
     const int64_t P = c->rows_pad;
-    c->ksplit = P >= 2048 ? 8 : int(P / 256);
+    c->ksplit = dense_ksplit(P, c->prec);
     const size_t cnt = size_t(P) * size_t(P);
     if (c->prec == FTH_FP64) {
         HIP_OK(c->dalloc(&c->d_m_hi, cnt * sizeof(double)));
@@ -306,10 +318,8 @@ fth_status upload_dense(fth_ctx* c, const std::vector<double>& M) {
         HIP_OK(hipMemcpy2D(tmp, size_t(P) * 4, mf.data(), size_t(n) * 4, size_t(n) * 4, size_t(n),
                            hipMemcpyHostToDevice));
     }
-    HIP_OK(c->dalloc(&c->d_m_hi, cnt * sizeof(uint16_t)));
-    HIP_OK(c->dalloc(&c->d_m_lo, cnt * sizeof(uint16_t)));
-    if (fth::launch_split_bf16(tmp, static_cast<uint16_t*>(c->d_m_hi), static_cast<uint16_t*>(c->d_m_lo),
-                               int64_t(cnt), c->stream) != 0)
+    HIP_OK(c->dalloc(&c->d_m_hi, cnt * 2 * sizeof(uint16_t)));  // hi and lo parts, tiled
+    if (fth::launch_split_bf16_tiled(tmp, c->d_m_hi, P, c->stream) != 0)
         return fail(FTH_EDEVICE, "bf16 split launch failed");
     HIP_OK(hipStreamSynchronize(c->stream));
     return FTH_OK;
@@ -490,7 +500,6 @@ fth::StepLaunch step_launch(fth_ctx* c) {
 fth::DenseGemmArgs gemm_args(fth_ctx* c, int k) {
     fth::DenseGemmArgs g{};
     g.m_hi = c->d_m_hi;
-    g.m_lo = c->d_m_lo;
     g.qt = c->d_qt;
     g.q0 = c->d_q[0];
     g.q1 = c->d_q[1];
@@ -918,7 +927,7 @@ size_t fth_footprint_bytes(const fth_matrix* M, int32_t ns, int32_t R, int64_t n
         bytes += n * size_t(R) * rb * 2 + 2 * ps_rows * size_t(R) * rb * size_t(1 + ns);
     } else {
         const size_t P = size_t(dense_rows_pad(int64_t(n)));
-        const size_t ks = P >= 2048 ? 8 : P / 256;
+        const size_t ks = size_t(dense_ksplit(int64_t(P), precision));
         bytes += P * P * (precision == FTH_FP32_BF16X3 ? 4 : rb);           // M (hi + lo, or FP64)
         bytes += 2 * P * size_t(R) * rb + 2 * ps_rows * size_t(R) * rb * size_t(1 + ns);  // q, (p, s) pairs
         bytes += ks * P * size_t(R) * rb;                                      // split-K partials

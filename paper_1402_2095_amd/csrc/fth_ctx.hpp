@@ -29,11 +29,10 @@ struct fth_ctx {
     void* d_val = nullptr;
     void* d_TS = nullptr;
     int32_t* d_pairs = nullptr;
-    // dense: M padded to rows_pad x rows_pad (bf16 hi/lo, or double), split-K partials, bf16 q split
+    // dense: M padded to rows_pad x rows_pad (bf16 hi/lo tiled, or double), split-K partials, bf16 q split
     int64_t rows_pad = 0;
     int ksplit = 1;
     void* d_m_hi = nullptr;
-    void* d_m_lo = nullptr;
     void* d_part = nullptr;
     uint16_t* d_qt = nullptr;
     bool qt_dirty = true;

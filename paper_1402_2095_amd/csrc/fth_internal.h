@@ -104,8 +104,8 @@ struct StepLaunch {
 
 // Arguments of the dense split-K force GEMM  part[ks] = M[:, kslice] q_n[kslice, :].
 struct DenseGemmArgs {
-    const void* m_hi;     // bf16 [rows_pad][rows_pad] (split form) or double (FP64 form)
-    const void* m_lo;     // bf16 [rows_pad][rows_pad] (split form only)
+    const void* m_hi;     // split form: bf16 hi and lo parts of M, tiled (see dense.hpp);
+                          // FP64 form: double [rows_pad][rows_pad]
     const uint16_t* qt;   // split form: q_n as bf16 hi/lo, tiled [rows_pad/8][R][2][8]
     const void* q0;       // FP64 form: q ping-pong buffers [rows_pad][R] (double)
     const void* q1;
@@ -155,7 +155,8 @@ template <typename Real>
 int launch_dense_epilogue(const StepArgs<Real>& a, const StepLaunch& L, int k, void* stream);
 int launch_gemm_bf16x3(const DenseGemmArgs& g, void* stream);
 int launch_gemm_f64(const DenseGemmArgs& g, void* stream);
-int launch_split_bf16(const float* m, uint16_t* hi, uint16_t* lo, int64_t count, void* stream);
+// M [P][P] FP32 -> bf16 hi/lo parts in the split GEMM's tiled layout (4 P^2 bytes at mt).
+int launch_split_bf16_tiled(const float* m, void* mt, int64_t P, void* stream);
 int launch_qt_from_q(const float* q, uint16_t* qt, int64_t N, int64_t rows_pad, int32_t R, void* stream);
 int launch_advance(int64_t* step_base, int64_t k, void* stream);
 // Trace estimators: sum the per-tile partials of K steps (fixed order), fold
