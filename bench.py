@@ -181,24 +181,26 @@ def source_hash(kind: str) -> str:
 
 
 def unit_of(kernel_name: str):
-    """The kernels of one timed unit, as rocprofv3 names them, its kind and
-    the steps it covers, from the library's description of the step."""
+    """The kernels of one timed unit, its kind and the steps it covers, from
+    the library's description of the step.  Kernel names are prefixes of
+    rocprofv3's names up to the last template argument the description fixes
+    (the trailing flags select optional estimators)."""
     import re
     m = re.search(r"tb_step_kernel<(\w+),NS=(\d+),RPT=4,KT=(\d+)>", kernel_name)
     if m:
         real, ns, kt = m.group(1), m.group(2), int(m.group(3))
-        return "tb", [f"tb_step_kernel<{real}, {ns}, 4, {kt}>", f"tb_pairs_kernel<{real}, 4, {kt}>"], kt
+        return "tb", [f"tb_step_kernel<{real}, {ns}, 4, {kt},", f"tb_pairs_kernel<{real}, 4, {kt}>"], kt
     m = re.search(r"csr_step_kernel<(\w+),NS=(\d+),RPT=(\d+),NT=(\d),CODED=(\d)>", kernel_name)
     if m:
         real, ns, rpt, nt, coded = m.groups()
         tf = {"0": "false", "1": "true"}
-        return "csr", [f"csr_step_kernel<{real}, {ns}, {rpt}, {tf[nt]}, {tf[coded]}>"], 1
+        return "csr", [f"csr_step_kernel<{real}, {ns}, {rpt}, {tf[nt]}, {tf[coded]},"], 1
     m = re.search(r"(gemm_bf16x3_kernel|gemm_f64_kernel)<RT=(\d+),ksplit=\d+> \+ "
                   r"dense_epilogue_kernel<(\w+),NS=(\d+),RPT=(\d+),NT=(\d)>", kernel_name)
     if m:
         gemm, rt, real, ns, rpt, nt = m.groups()
         return "dense", [f"{gemm}<{rt}>", f"dense_epilogue_kernel<{real}, {ns}, {rpt}, "
-                                          f"{'true' if nt == '1' else 'false'}>"], 1
+                                          f"{'true' if nt == '1' else 'false'},"], 1
     return None, [], 1
 
 
