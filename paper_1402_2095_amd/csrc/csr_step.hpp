@@ -39,7 +39,12 @@ namespace dev {
 __device__ __forceinline__ bool noise_first() { return ((blockIdx.x + (threadIdx.x >> 6)) & 1) != 0; }
 
 // One row of one request: gather, noise, force, shared row update.
-template <typename Real, int NS, int RPT, bool NT>
+// LONG: rows of more than 16 entries (the M1 lattice has 81).  Past the first
+// batch, such rows gather GL entries per batch instead of four: each batch is
+// a chain of two dependent loads (column indices, then the rows they name),
+// so a long row costs (nnz - 4) / GL chains instead of (nnz - 4) / 4.  The
+// products are still added in stored order, so the result is the same.
+template <typename Real, int NS, int RPT, bool NT, bool LONG = false>
 __device__ __forceinline__ void csr_row(const StepArgs<Real>& a, const StepInfo& si, int64_t i, const Real* qr,
                                         Real* qw, double* trow) {
     using V = Vec<Real, RPT>;
@@ -47,6 +52,7 @@ __device__ __forceinline__ void csr_row(const StepArgs<Real>& a, const StepInfo&
     // CSR entries gathered per batch: four keeps the kernel near 80 VGPRs (six waves
     // per SIMD), which measured faster than eight entries at 92-114 VGPRs
     constexpr int G = 4;
+    constexpr int GL = LONG ? (RPT >= 8 ? 8 : 16) : G;
     Real xi[NS + 1][RPT];
     const bool early = noise_first();
     if (early) row_noise<Real, NS, RPT>(a, si, i, xi);
@@ -74,20 +80,27 @@ __device__ __forceinline__ void csr_row(const StepArgs<Real>& a, const StepInfo&
 #pragma unroll
             for (int m = 0; m < RPT; ++m) acc[m] = fmaR(vj[u], qj[u].v[m], acc[m]);
         }
-    for (int64_t base = kb + G; base < ke; base += G) {  // rows longer than one batch
+    for (int64_t base = kb + G; base < ke; base += GL) {  // rows longer than one batch
+        V ql[GL];
+        Real vl[GL];
+        int32_t cl[GL];
 #pragma unroll
-        for (int u = 0; u < G; ++u) {
-            vj[u] = Real(0);
+        for (int u = 0; u < GL; ++u) {
+            vl[u] = Real(0);
+            cl[u] = 0;
             if (base + u < ke) {
-                vj[u] = a.val[base + u];
-                qj[u] = load_vec<Real, RPT>(qr + int64_t(a.col[base + u]) * R + si.r0);
+                vl[u] = a.val[base + u];
+                cl[u] = a.col[base + u];
             }
         }
 #pragma unroll
-        for (int u = 0; u < G; ++u)
+        for (int u = 0; u < GL; ++u)
+            if (base + u < ke) ql[u] = load_vec<Real, RPT>(qr + int64_t(cl[u]) * R + si.r0);
+#pragma unroll
+        for (int u = 0; u < GL; ++u)
             if (base + u < ke) {
 #pragma unroll
-                for (int m = 0; m < RPT; ++m) acc[m] = fmaR(vj[u], qj[u].v[m], acc[m]);
+                for (int m = 0; m < RPT; ++m) acc[m] = fmaR(vl[u], ql[u].v[m], acc[m]);
             }
     }
     (void)finish_row<Real, NS, RPT, NT>(a, si, i, st, acc, xi, qw, trow);
@@ -154,7 +167,8 @@ __device__ __forceinline__ void coded_row(const StepArgs<Real>& a, const StepInf
 
 // TR: trace partials are kept (a separate instantiation, so the common form
 // carries none of their code or registers).
-template <typename Real, int NS, int RPT, bool NT, bool CODED, bool TR>
+// LONG: the plain form with long-row gather batches (see csr_row).
+template <typename Real, int NS, int RPT, bool NT, bool CODED, bool TR, bool LONG = false>
 __global__ __launch_bounds__(256) void csr_step_kernel(const StepArgs<Real> a, const int k) {
     const StepInfo si = step_info<Real, RPT>(a, k);
     const Real* __restrict__ qr = (si.n & 1) ? a.q1 : a.q0;
@@ -184,7 +198,7 @@ __global__ __launch_bounds__(256) void csr_step_kernel(const StepArgs<Real> a, c
         if constexpr (CODED)
             coded_row<Real, NS, RPT, NT>(a, si, i, qr, qw, s_off, s_val, trow);
         else
-            csr_row<Real, NS, RPT, NT>(a, si, i, qr, qw, trow);
+            csr_row<Real, NS, RPT, NT, LONG>(a, si, i, qr, qw, trow);
     }
     if constexpr (TR) {
         __syncthreads();
@@ -237,12 +251,21 @@ struct CsrKernels {
             return reinterpret_cast<const void*>(&csr_step_kernel<Real, NS, RPT, NT, false, TR>);
         }
     };
-    // The coded form is instantiated for 4 and 8 replicas per thread only.
+    // The coded and long-row forms are instantiated for 4 and 8 replicas per thread only.
     template <typename Real, int NS, int RPT, bool NT>
     struct Coded {
         static const void* fn() {
             if constexpr (RPT >= 4)
                 return reinterpret_cast<const void*>(&csr_step_kernel<Real, NS, RPT, NT, true, TR>);
+            else
+                return nullptr;
+        }
+    };
+    template <typename Real, int NS, int RPT, bool NT>
+    struct Long {
+        static const void* fn() {
+            if constexpr (RPT >= 4)
+                return reinterpret_cast<const void*>(&csr_step_kernel<Real, NS, RPT, NT, false, TR, true>);
             else
                 return nullptr;
         }
@@ -270,8 +293,9 @@ template <typename Real, bool TR>
 int launch_csr_step_impl(const StepArgs<Real>& a, const StepLaunch& L, int k, void* stream) {
     if (TR != (a.tpart != nullptr)) return -4;
     using KS = dev::CsrKernels<TR>;
-    const void* fn = L.coded ? dev::pick_kernel<KS::template Coded, Real>(L)
-                             : dev::pick_kernel<KS::template Plain, Real>(L);
+    const void* fn = L.coded       ? dev::pick_kernel<KS::template Coded, Real>(L)
+                     : L.long_rows ? dev::pick_kernel<KS::template Long, Real>(L)
+                                   : dev::pick_kernel<KS::template Plain, Real>(L);
     return dev::launch_step_kernel<Real>(fn, a, L, k, stream);
 }
 

@@ -491,9 +491,14 @@ fth::StepArgs<Real> step_args(fth_ctx* c) {
     return a;
 }
 
+// Plain CSR rows longer than 16 entries take the long-row gather batches.
+bool long_rows(const fth_ctx* c) {
+    return !c->dense() && !(c->coded && c->rpt >= 4) && c->rpt >= 4 && c->max_row_nnz > 16;
+}
+
 fth::StepLaunch step_launch(fth_ctx* c) {
     const int per_block = c->block / (c->R / c->rpt);
-    return fth::StepLaunch{c->ns, c->rpt, c->nt, c->coded && c->rpt >= 4, c->block,
+    return fth::StepLaunch{c->ns, c->rpt, c->nt, c->coded && c->rpt >= 4, long_rows(c), c->block,
                            (c->npairs + per_block - 1) / per_block};
 }
 
@@ -1303,9 +1308,10 @@ fth_status fth_kernel_name(const fth_ctx* c, char* name, size_t len) {
                       c->prec == FTH_FP64 ? "double" : "float", c->ns, c->tb_kt, c->tb_block, c->block,
                       c->tuned ? " (autotuned)" : "");
     else
-        std::snprintf(name, len, "csr_step_kernel<%s,NS=%d,RPT=%d,NT=%d,CODED=%d> block=%d%s",
+        std::snprintf(name, len, "csr_step_kernel<%s,NS=%d,RPT=%d,NT=%d,CODED=%d> block=%d%s%s",
                       c->prec == FTH_FP64 ? "double" : "float", c->ns, c->rpt, int(c->nt),
-                      int(c->coded && c->rpt >= 4), c->block, c->tuned ? " (autotuned)" : "");
+                      int(c->coded && c->rpt >= 4), c->block, long_rows(c) ? " (long-row batches)" : "",
+                      c->tuned ? " (autotuned)" : "");
     return FTH_OK;
 }
 

@@ -98,6 +98,7 @@ struct StepLaunch {
     int rpt;             // replicas per thread (template: 1, 2, 4, 8)
     bool nt;             // streaming (non-temporal) state loads/stores (template)
     bool coded;          // coded sparse form (template; replicas per thread 4 or 8)
+    bool long_rows;      // plain CSR with long-row gather batches (template; replicas per thread 4 or 8)
     int block;           // threads per workgroup
     int64_t pair_tiles;  // extra workgroups for the selected pairs
 };

@@ -55,6 +55,8 @@ def test_noise_words_bit_exact_and_normals():
 def make_case(kind, n):
     if kind == "lap":
         return fi.laplacian3d_csr(n, 0.1, dtype=np.float64)
+    if kind == "m1":   # the paper's M1 lattice: 81 entries per row (long-row gather batches)
+        return fi.m1_lattice_csr(n, 3, dtype=np.float64)
     return fi.banded_spd_csr(n, 3003 + n, dtype=np.float64)
 
 
@@ -68,6 +70,8 @@ CASES = [
     ("band301-ns1-R2-fp32", "band", 301, "rand1", 2, fth.FTH_FP32, True),
     ("band257-ns7-R16-fp64", "band", 257, "rand7", 16, fth.FTH_FP64, True),
     ("lap4-invsqrt-R512-fp32", "lap", 4, "invsqrt_ns4", 512, fth.FTH_FP32, False),
+    ("m1-6-invsqrt-R8-fp32", "m1", 6, "invsqrt_ns4", 8, fth.FTH_FP32, True),
+    ("m1-6-rand3-R32-fp64", "m1", 6, "rand3", 32, fth.FTH_FP64, True),
 ]
 
 
@@ -88,6 +92,8 @@ def test_trajectory_parity(case):
     M = make_case(kind, size)
     A, C = gle_for(gname)
     lam_max = fi.laplacian3d_lambda_max(size, 0.1) if kind == "lap" else fi.gershgorin_max(M)
+    if kind == "m1":
+        assert int(np.max(np.diff(M.row_ptr))) == 81
     h = fi.dt_rule(lam_max)
     pairs = fi.random_pairs(M.n, 64, 11)
     seed, stream, burn, L = 123456789, 3, 5, 7
@@ -127,6 +133,9 @@ def test_trajectory_parity(case):
     assert normwise(est, m_o) <= 10 * TOL[prec]
     finite = np.isfinite(se_o)
     assert normwise(se[finite], se_o[finite]) <= (1e-2 if prec == fth.FTH_FP32 else 1e-6)
+    if kind == "m1":
+        print(f"  kernel: {sol.kernel_name}", flush=True)
+        assert "long-row batches" in sol.kernel_name
     sol.close()
 
 

@@ -28,8 +28,9 @@ def dense_case(n, seed=4004):
 
 
 @pytest.mark.parametrize("prec", [fth.FTH_FP64, fth.FTH_FP32_BF16X3], ids=["fp64", "bf16x3"])
-# 2195 pads to 2560: eight K slices of 320 (whole 64-wide k-steps)
-@pytest.mark.parametrize("n,R", [(300, 16), (1000, 32), (520, 128), (2195, 64)])
+# 2195 pads to 2560: eight K slices of 320 (whole 64-wide k-steps); 9000 pads to 9216, where the
+# split form takes four K slices of 2304 (72 row blocks x 4 = 288 workgroups, one round)
+@pytest.mark.parametrize("n,R", [(300, 16), (1000, 32), (520, 128), (2195, 64), (9000, 16)])
 def test_force_against_fp64_gemm(prec, n, R):
     M, h = dense_case(n)
     g = fi.load_gle("invsqrt_ns4")
@@ -42,8 +43,11 @@ def test_force_against_fp64_gemm(prec, n, R):
     ref = -(M.astype(np.float64) @ q)
     err = normwise(F, ref)
     rel_rows = np.max(np.abs(F - ref), axis=0) / np.max(np.abs(ref), axis=0)
-    print(f"[force] n={n} R={R} prec={prec}: normwise {err:.2e}, worst column {rel_rows.max():.2e}", flush=True)
+    print(f"[force] n={n} R={R} prec={prec}: normwise {err:.2e}, worst column {rel_rows.max():.2e} "
+          f"({sol.kernel_name})", flush=True)
     assert err <= (1e-13 if prec == fth.FTH_FP64 else 3e-5)
+    if n == 9000:
+        assert ("ksplit=4" if prec == fth.FTH_FP32_BF16X3 else "ksplit=8") in sol.kernel_name
     sol.close()
 
 
