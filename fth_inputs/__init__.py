@@ -324,13 +324,6 @@ def load_gle(name_or_path: str) -> GLE:
     return GLE(ns, A, C, d)
 
 
-def scaled_gle(g: GLE, alpha: float, gamma: float) -> GLE:
-    """(alpha A_p, gamma C_p): the parameter scaling of the paper's Sec. I."""
-    meta = dict(g.meta)
-    meta["scaled"] = {"alpha": alpha, "gamma": gamma}
-    return GLE(g.ns, alpha * g.A_p, gamma * g.C_p, meta)
-
-
 # --------------------------------------------------------------------------
 # Serving mix
 # --------------------------------------------------------------------------

@@ -28,8 +28,25 @@ def hipcc() -> str:
     return shutil.which("hipcc") or "/opt/rocm/bin/hipcc"
 
 
-def _compile(src: str) -> str:
+def _deps_mtime(path: str, seen=None) -> float:
+    """Newest modification time of a source and the local headers it
+    includes (quoted includes, followed recursively)."""
+    import re
+    seen = set() if seen is None else seen
+    if path in seen or not os.path.exists(path):
+        return 0.0
+    seen.add(path)
+    t = os.path.getmtime(path)
+    with open(path) as fh:
+        for inc in re.findall(r'^\s*#\s*include\s+"([^"]+)"', fh.read(), re.M):
+            t = max(t, _deps_mtime(os.path.normpath(os.path.join(os.path.dirname(path), inc)), seen))
+    return t
+
+
+def _compile(src: str, incremental: bool = False) -> str:
     obj = os.path.join(BUILD, os.path.basename(src) + ".o")
+    if incremental and os.path.exists(obj) and os.path.getmtime(obj) > _deps_mtime(src):
+        return obj
     cmd = [hipcc(), *COMMON, *DEVICE, "-I", CSRC, "-c", src, "-o", obj]
     if src.endswith(".cpp"):
         cmd = [hipcc(), *COMMON, "-x", "hip", *DEVICE, "-I", CSRC, "-c", src, "-o", obj]
@@ -43,12 +60,14 @@ def sources():
     return sorted(os.path.join(CSRC, f) for f in os.listdir(CSRC) if f.endswith((".hip", ".cpp")))
 
 
-def build(verbose: bool = True, jobs: int | None = None) -> str:
+def build(verbose: bool = True, jobs: int | None = None, incremental: bool = False) -> str:
+    """Compile every source (incremental=True skips objects newer than their
+    source and every header) and link the library."""
     os.makedirs(BUILD, exist_ok=True)
     srcs = sources()
     jobs = jobs or min(len(srcs), int(os.environ.get("MAX_JOBS", os.cpu_count() or 4)), 16)
     with cf.ThreadPoolExecutor(max_workers=jobs) as ex:
-        objs = list(ex.map(_compile, srcs))
+        objs = list(ex.map(lambda f: _compile(f, incremental), srcs))
     tmp = LIB + ".tmp"
     cmd = [hipcc(), f"--offload-arch={ARCH}", "-shared", "-fPIC", *objs, "-o", tmp]
     res = subprocess.run(cmd, capture_output=True, text=True)
@@ -61,5 +80,5 @@ def build(verbose: bool = True, jobs: int | None = None) -> str:
 
 
 if __name__ == "__main__":
-    build()
+    build(incremental="--incremental" in sys.argv)
     sys.exit(0)

@@ -33,6 +33,19 @@ fth_status fail(fth_status st, const char* fmt, ...) {
 }
 
 
+uint64_t hash_words(const void* p, size_t bytes, uint64_t seed) {
+    uint64_t h = seed ? seed : 1469598103934665603ull;
+    const unsigned char* b = static_cast<const unsigned char*>(p);
+    size_t k = 0;
+    for (; k + 8 <= bytes; k += 8) {
+        uint64_t w;
+        std::memcpy(&w, b + k, 8);
+        h = (h ^ w) * 1099511628211ull;
+    }
+    for (; k < bytes; ++k) h = (h ^ b[k]) * 1099511628211ull;
+    return h;
+}
+
 constexpr int kDefaultGraphSteps = 64;
 constexpr int kTbMaxSteps = 5;   // longest temporally blocked launch (snapshot depth)
 constexpr int64_t kTbMaxW = 16;  // widest half-bandwidth blocked
@@ -717,12 +730,15 @@ fth_status build_graph(fth_ctx* c, int K) {
 // replicas per thread, streaming state access.  Each candidate runs a few
 // steps on the live state, which is saved before and restored after, so
 // tuning leaves the trajectory untouched.  The winner is cached per shape
-// key (precision, n, nnz, R, ns).
+// key: precision, GLE size, R, n, nnz, half-bandwidth, longest row and
+// whether momentum-form or trace accumulators are kept (they lower the
+// largest blocked workgroup).
 struct TuneKey {
-    int prec, ns, R;
-    int64_t n, nnz;
+    int prec, ns, R, xtra, max_row_nnz;
+    int64_t n, nnz, band_w;
     bool operator<(const TuneKey& o) const {
-        return std::tie(prec, ns, R, n, nnz) < std::tie(o.prec, o.ns, o.R, o.n, o.nnz);
+        return std::tie(prec, ns, R, xtra, max_row_nnz, n, nnz, band_w) <
+               std::tie(o.prec, o.ns, o.R, o.xtra, o.max_row_nnz, o.n, o.nnz, o.band_w);
     }
 };
 struct TuneChoice {
@@ -759,9 +775,11 @@ fth_status autotune(fth_ctx* c) {
     const bool try_tb = c->opt.temporal_steps == 0 && (tb_eligible(c, 3, 1024) || tb_eligible(c, 3, 512) ||
                                                        tb_eligible(c, 3, 256));
     // (KT = 5 is eligible only where KT = 3 is.)
-    const TuneKey key{c->prec, c->ns, c->R, c->n, c->nnz};
+    const TuneKey key{c->prec, c->ns, c->R, (c->opt.acc_pp || c->opt.acc_trace) ? 1 : 0, c->max_row_nnz,
+                      c->n, c->nnz, c->band_w};
     auto hit = tune_cache().find(key);
-    if (hit != tune_cache().end() && (hit->second.tb_kt == 0 || try_tb)) {
+    if (hit != tune_cache().end() &&
+        (hit->second.tb_kt == 0 || (try_tb && tb_eligible(c, hit->second.tb_kt, hit->second.tb_block)))) {
         c->block = hit->second.block;
         c->rpt = hit->second.rpt;
         c->nt = hit->second.nt;
@@ -1010,6 +1028,19 @@ fth_status fth_create(const fth_matrix* M_in, const fth_gle* gle_in, double dt, 
     c->opt = opt;
     c->npairs = npairs;
     c->nnz = M->nnz;
+    {
+        const size_t vb = M->value_is_f64 ? 8 : 4;
+        uint64_t mh = hash_words(&M->n, sizeof(M->n), uint64_t(M->format) + 1);
+        if (M->format == FTH_DENSE) {
+            mh = hash_words(M->dense, size_t(M->n) * size_t(M->n) * vb, mh);
+        } else {
+            mh = hash_words(M->row_ptr, sizeof(int64_t) * size_t(M->n + 1), mh);
+            mh = hash_words(M->col, sizeof(int32_t) * size_t(M->nnz), mh);
+            mh = hash_words(M->val, vb * size_t(M->nnz), mh);
+        }
+        c->m_hash = hash_words(&M->value_is_f64, sizeof(M->value_is_f64), mh);
+        c->pair_hash = npairs > 0 ? hash_words(pairs, sizeof(int32_t) * size_t(2 * npairs), 7) : 7;
+    }
     st = make_propagator(gle, dt, c->T, c->S);
     if (st != FTH_OK) return st;
 
@@ -1318,19 +1349,35 @@ fth_status fth_kernel_name(const fth_ctx* c, char* name, size_t len) {
 size_t fth_device_bytes(const fth_ctx* c) { return c ? c->device_bytes() : 0; }
 
 namespace {
+// Image layout (version 2): this header, q_n, (p, s)_n, the accumulators,
+// then an FNV-1a checksum of everything before it.  The header records every
+// parameter a continuation depends on, so an image is only accepted by a
+// context that would have produced the same trajectory and estimates.
 struct SaveHeader {
     char magic[8];
     uint32_t version, prec;
     int64_t n, R, ns, n_out, step, q_bytes, ps_bytes;
     uint64_t seed;
     uint32_t stream_id, poisoned;
+    int64_t burn_in, block_len;
+    double h;
+    uint32_t acc_diag, acc_pp, acc_trace, reserved;
+    uint64_t ts_hash;    // propagator T and S as used (FP64)
+    uint64_t m_hash;     // matrix as used (after the spectral map), pattern and values
+    uint64_t pair_hash;  // selected pairs in input order
 };
+constexpr uint32_t kSaveVersion = 2;
 constexpr char kSaveMagic[8] = {'F', 'T', 'H', 'S', 'T', 'A', 'T', 'E'};
 
 uint64_t fnv1a(const unsigned char* p, size_t n) {
     uint64_t h = 1469598103934665603ull;
     for (size_t k = 0; k < n; ++k) h = (h ^ p[k]) * 1099511628211ull;
     return h;
+}
+
+uint64_t ts_hash(const fth_ctx* c) {
+    uint64_t hsh = hash_words(c->T.data(), c->T.size() * sizeof(double), 0);
+    return hash_words(c->S.data(), c->S.size() * sizeof(double), hsh);
 }
 
 size_t image_bytes(const fth_ctx* c) {
@@ -1351,7 +1398,7 @@ fth_status fth_save(fth_ctx* c, void* buf, size_t* len) {
     HIP_OK(hipStreamSynchronize(c->stream));
     SaveHeader hd{};
     std::memcpy(hd.magic, kSaveMagic, 8);
-    hd.version = 1;
+    hd.version = kSaveVersion;
     hd.prec = uint32_t(c->prec);
     hd.n = c->n;
     hd.R = c->R;
@@ -1363,6 +1410,15 @@ fth_status fth_save(fth_ctx* c, void* buf, size_t* len) {
     hd.seed = c->opt.seed;
     hd.stream_id = c->opt.stream_id;
     hd.poisoned = c->poisoned ? 1u : 0u;
+    hd.burn_in = c->opt.burn_in;
+    hd.block_len = c->opt.block_len;
+    hd.h = c->h;
+    hd.acc_diag = c->opt.acc_diag ? 1u : 0u;
+    hd.acc_pp = c->opt.acc_pp ? 1u : 0u;
+    hd.acc_trace = c->opt.acc_trace ? 1u : 0u;
+    hd.ts_hash = ts_hash(c);
+    hd.m_hash = c->m_hash;
+    hd.pair_hash = c->pair_hash;
     unsigned char* out = static_cast<unsigned char*>(buf);
     std::memcpy(out, &hd, sizeof(hd));
     size_t off = sizeof(hd);
@@ -1384,7 +1440,9 @@ fth_status fth_load(fth_ctx* c, const void* buf, size_t len) {
     if (len < sizeof(SaveHeader) + sizeof(uint64_t)) return fail(FTH_EINVAL, "image too short");
     SaveHeader hd;
     std::memcpy(&hd, buf, sizeof(hd));
-    if (std::memcmp(hd.magic, kSaveMagic, 8) != 0 || hd.version != 1) return fail(FTH_EINVAL, "not a state image");
+    if (std::memcmp(hd.magic, kSaveMagic, 8) != 0) return fail(FTH_EINVAL, "not a state image");
+    if (hd.version != kSaveVersion)
+        return fail(FTH_EINVAL, "state image version %u is not supported (expected %u)", hd.version, kSaveVersion);
     if (hd.R < 1 || hd.R > 512) return fail(FTH_EINVAL, "damaged image (replicas)");
     fth_status st = ensure_state(c, int32_t(hd.R));
     if (st != FTH_OK) return st;
@@ -1395,6 +1453,15 @@ fth_status fth_load(fth_ctx* c, const void* buf, size_t len) {
         return fail(FTH_EINVAL, "image was saved from a context of another shape");
     if (hd.seed != c->opt.seed || hd.stream_id != c->opt.stream_id)
         return fail(FTH_EINVAL, "image was saved with another noise stream (seed or stream id)");
+    if (hd.burn_in != c->opt.burn_in || hd.block_len != c->opt.block_len)
+        return fail(FTH_EINVAL, "image was saved with another burn-in or block length");
+    if (hd.h != c->h || hd.ts_hash != ts_hash(c))
+        return fail(FTH_EINVAL, "image was saved with another time step or GLE");
+    if (hd.acc_diag != (c->opt.acc_diag ? 1u : 0u) || hd.acc_pp != (c->opt.acc_pp ? 1u : 0u) ||
+        hd.acc_trace != (c->opt.acc_trace ? 1u : 0u))
+        return fail(FTH_EINVAL, "image was saved with other accumulators");
+    if (hd.m_hash != c->m_hash) return fail(FTH_EINVAL, "image was saved for another matrix");
+    if (hd.pair_hash != c->pair_hash) return fail(FTH_EINVAL, "image was saved for other pairs");
     if (hd.step < 0 || hd.step >= (int64_t(1) << 32)) return fail(FTH_EINVAL, "damaged image (step)");
     const unsigned char* in = static_cast<const unsigned char*>(buf);
     uint64_t sum;

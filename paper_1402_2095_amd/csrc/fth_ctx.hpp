@@ -85,6 +85,8 @@ struct fth_ctx {
     int gK = 0;
     int64_t step = 0;
     bool poisoned = false;
+    uint64_t m_hash = 0;     // hash of the matrix as used (recorded in state images)
+    uint64_t pair_hash = 0;  // hash of the selected pairs
     double last_ms = 0.0;
     int device = 0;
 
@@ -176,6 +178,10 @@ namespace fth {
 namespace host {
 
 fth_status fail(fth_status st, const char* fmt, ...);
+// 64-bit hash of a byte range (FNV-1a over 8-byte words, then the tail
+// bytes), continuing from seed (0: a fresh hash).  Identifies inputs in
+// state images; not a checksum against deliberate changes.
+uint64_t hash_words(const void* p, size_t bytes, uint64_t seed);
 extern thread_local std::string g_last_error;
 
 fth_status check_csr(const fth_matrix* M);

@@ -75,6 +75,38 @@ def test_load_rejects_other_streams_and_damage():
     assert e.value.status == fth.FTH_EINVAL
 
 
+def test_load_rejects_other_parameters():
+    """The image records every parameter a continuation depends on: block
+    length, burn-in, time step, GLE, accumulators, matrix values and pairs.
+    A context that differs in any of them rejects it (the estimates would
+    otherwise be formed from blocks of another length, or the trajectory
+    would continue under other dynamics)."""
+    g = fi.load_gle("invsqrt_ns4")
+    g2 = fi.load_gle("fermi_b20_ns4")
+    M = fi.banded_spd_csr(3000, 2)
+    h = fi.dt_rule(fi.gershgorin_max(M))
+    pairs = fi.random_pairs(M.n, 8, 3)
+    base = dict(replicas=8, seed=1, pairs=pairs, block_len=10, acc_diag=True)
+    image = fth.Solver(M, g.A_p, g.C_p, h, **base).run(25).save()
+    fth.Solver(M, g.A_p, g.C_p, h, **base).load(image).close()   # same parameters: accepted
+    M2 = fi.CSR(M.n, M.row_ptr, M.col, M.val * np.float32(1.0001))
+    variants = [
+        ((M, g.A_p, g.C_p, h), dict(base, block_len=20)),
+        ((M, g.A_p, g.C_p, h), dict(base, burn_in=5)),
+        ((M, g.A_p, g.C_p, 0.9 * h), base),
+        ((M, g2.A_p, g2.C_p, h), base),
+        ((M, g.A_p, g.C_p, h), dict(base, acc_pp=True, acc_diag=False)),
+        ((M2, g.A_p, g.C_p, h), base),
+        ((M, g.A_p, g.C_p, h), dict(base, pairs=pairs[::-1].copy())),
+    ]
+    for args, kw in variants:
+        s = fth.Solver(*args, **kw)
+        with pytest.raises(fth.FthError) as e:
+            s.load(image)
+        assert e.value.status == fth.FTH_EINVAL, kw
+        s.close()
+
+
 def test_footprint_matches_held_memory():
     g = fi.load_gle("invsqrt_ns4")
     M = fi.banded_spd_csr(50000, 6)

@@ -140,50 +140,76 @@ def test_trajectory_parity(case):
 
 
 # ------------------------------------------------ full-size configurations
+def compare_full_state(sol, orc, tol, label):
+    q, p, s = sol.state()
+    blk, s1, s2, nb, step = sol.accumulators()
+    assert step == orc.step
+    for name, a, b in (("q", q, orc.q), ("p", p, orc.p), ("s", s, orc.s), ("acc", s1 + blk, orc.s1 + orc.blk),
+                       ("s2", s2, orc.s2)):
+        if not np.any(b):
+            assert not np.any(a), name
+            continue
+        e = normwise(a, b)
+        print(f"  {label} step {step} {name}: {e:.2e}", flush=True)
+        assert e <= tol, (label, step, name)
+
+
 @pytest.mark.parametrize("prec", [fth.FTH_FP32, fth.FTH_FP64], ids=["fp32", "fp64"])
 def test_laplacian_64cubed_full_size(prec):
-    """64^3 periodic Laplacian + 0.1, R = 8, diagonal + 1024 pairs: the whole
-    state after 12 steps (6 graph launches of 2 steps) against the oracle."""
+    """64^3 periodic Laplacian + 0.1, R = 8, diagonal + 1024 pairs, in the
+    benchmark's launch configuration (autotuned shape, 64-step graphs and
+    direct tails): the whole state and the accumulators against the oracle
+    after 1, 10, 100 and (FP32) 1000 steps."""
     print(f"[fullsize] laplacian 64^3 prec={prec}", flush=True)
     M = fi.laplacian3d_csr(64, 0.1)
     g = fi.load_gle("invsqrt_ns4")
     h = fi.dt_rule(fi.laplacian3d_lambda_max(64, 0.1))
     pairs = fi.random_pairs(M.n, 1024, 2002)
     sol = fth.Solver(M, g.A_p, g.C_p, h, pairs=pairs, replicas=8, precision=prec, seed=2, acc_diag=True,
-                     steps_per_graph=2)
+                     steps_per_graph=64, block_len=100, tune=True)
     M64 = fi.CSR(M.n, M.row_ptr, M.col, M.val.astype(np.float64))
-    orc = oracle.OracleRun(M64, g.A_p, g.C_p, h, 8, np.concatenate([pairs, fi.diag_pairs(M.n)]), seed=2)
-    sol.run(12)
-    orc.run(12)
-    q, p, s = sol.state()
-    blk, s1, s2, nb, step = sol.accumulators()
-    for name, a, b in (("q", q, orc.q), ("p", p, orc.p), ("s", s, orc.s), ("acc", s1 + blk, orc.s1 + orc.blk)):
-        e = normwise(a, b)
-        print(f"  {name}: {e:.2e}", flush=True)
-        assert e <= TOL[prec], name
+    orc = oracle.OracleRun(M64, g.A_p, g.C_p, h, 8, np.concatenate([pairs, fi.diag_pairs(M.n)]), seed=2,
+                           block_len=100)
+    checkpoints = (1, 10, 100, 1000) if prec == fth.FTH_FP32 else (1, 10, 100)
+    done = 0
+    for c in checkpoints:
+        sol.run(c - done)
+        orc.run(c - done)
+        done = c
+        compare_full_state(sol, orc, TOL[prec], "lap64")
+    print(f"  kernel: {sol.kernel_name}", flush=True)
+    est, se, nsamp = sol.read()
+    m_o, se_o = orc.estimates()
+    assert normwise(est, m_o) <= 10 * TOL[prec]
     sol.close()
 
 
-def test_banded_1e6_full_size_sampled():
-    """Banded SPD N = 1e6, R = 32, Fermi GLE, FP32: four steps through the
-    captured graph; the full state is compared."""
-    print("[fullsize] banded 1e6 R=32", flush=True)
+def test_banded_1e6_full_size_blocked():
+    """Banded SPD N = 1e6, R = 32, Fermi GLE, FP32, diagonal + 1024 pairs, in
+    the benchmark's blocked launch shape (5 steps per launch, 1024-thread
+    workgroups, 20-step graphs): the whole state and the accumulators against
+    the oracle after 5 and 100 steps."""
+    print("[fullsize] banded 1e6 R=32 blocked KT=5", flush=True)
     M = fi.banded_spd_csr(1_000_000, 3003)
     g = fi.load_gle("fermi_b20_ns4")
     h = fi.dt_rule(fi.gershgorin_max(M))
     pairs = fi.random_pairs(M.n, 1024, 3004)
     sol = fth.Solver(M, g.A_p, g.C_p, h, pairs=pairs, replicas=32, precision=fth.FTH_FP32, seed=4,
-                     acc_diag=True, steps_per_graph=2)
+                     acc_diag=True, steps_per_graph=20, block_len=10, temporal_steps=5, temporal_threads=1024)
     M64 = fi.CSR(M.n, M.row_ptr, M.col, M.val.astype(np.float64))
-    orc = oracle.OracleRun(M64, g.A_p, g.C_p, h, 32, np.concatenate([pairs, fi.diag_pairs(M.n)]), seed=4)
-    sol.run(4)
-    orc.run(4)
-    q, p, s = sol.state()
-    blk, s1, s2, nb, step = sol.accumulators()
-    for name, a, b in (("q", q, orc.q), ("p", p, orc.p), ("s", s, orc.s), ("acc", s1 + blk, orc.s1 + orc.blk)):
-        e = normwise(a, b)
-        print(f"  {name}: {e:.2e}", flush=True)
-        assert e <= 1e-4, name
+    orc = oracle.OracleRun(M64, g.A_p, g.C_p, h, 32, np.concatenate([pairs, fi.diag_pairs(M.n)]), seed=4,
+                           block_len=10)
+    done = 0
+    for c in (5, 100):
+        sol.run(c - done)
+        orc.run(c - done)
+        done = c
+        compare_full_state(sol, orc, 1e-4, "band1e6")
+    print(f"  kernel: {sol.kernel_name}", flush=True)
+    assert "KT=5" in sol.kernel_name and "block=1024" in sol.kernel_name
+    est, se, nsamp = sol.read()
+    m_o, se_o = orc.estimates()
+    assert normwise(est, m_o) <= 1e-3
     sol.close()
 
 

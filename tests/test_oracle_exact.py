@@ -143,3 +143,34 @@ def test_gh_p_converges_to_g0_p_second_order():
     e2 = np.abs(exact.gh_p(lam, A, C, 0.01) - exact.g0_p(lam, A, C))
     ratio = e1 / e2
     assert np.all((ratio > 3.5) & (ratio < 4.5)), ratio
+
+
+def test_tau_slowest_white_noise_closed_form():
+    """Langevin thermostat (ns = 0, friction gamma): a mode's relaxation
+    rates are the roots of mu^2 - gamma mu + lambda = 0, so the slowest time
+    is 2 / gamma when underdamped (gamma^2 < 4 lambda) and
+    2 / (gamma - sqrt(gamma^2 - 4 lambda)) when overdamped."""
+    for gamma in (0.3, 1.0, 4.0):
+        lam = np.geomspace(0.01, 50, 23)
+        disc = gamma * gamma - 4 * lam
+        want = np.where(disc < 0, 2.0 / gamma, 2.0 / (gamma - np.sqrt(np.maximum(disc, 0.0))))
+        assert np.allclose(exact.tau_slowest(lam, np.array([[gamma]])), want, rtol=1e-10)
+
+
+@pytest.mark.parametrize("name", ["invsqrt_ns4", "fermi_b20_ns4", "ln_ns4"])
+def test_tau_slowest_from_discrete_step_map(name):
+    """Independent route: the one-step map G of the integrated dynamics
+    (kick, exact OU step exp(-A_p h), kick, drift) has spectral radius
+    exp(-h / tau) + O(h^2), so -h / ln rho(G) tends to the slowest
+    relaxation time as h -> 0 (first order in h)."""
+    g = fth_inputs.load_gle(name)
+    lo, hi = g.meta["window_lambda"]
+    for lam in np.geomspace(lo, hi, 5):
+        want = float(exact.tau_slowest(lam, g.A_p)[0])
+        errs = []
+        for h in (2e-3 / np.sqrt(hi), 1e-3 / np.sqrt(hi)):
+            T, S = oracle.propagator(g.A_p, g.C_p, h)
+            rho = exact.spectral_radius(lam, T, S, h)
+            errs.append(abs(-h / np.log(rho) / want - 1.0))
+        assert errs[1] < 2e-3, (lam, errs)
+        assert errs[1] < 0.75 * errs[0] + 1e-9  # shrinks with h
