@@ -39,6 +39,7 @@ CSRC = os.path.join(ROOT, "paper_1402_2095_amd", "csrc")
 KERNEL_SOURCES = {
     "csr": ["csr_step.hpp", "csr_step_f32.hip", "csr_step_f64.hip", "row_update.hpp", "noise.hpp"],
     "tb": ["tb_step.hpp", "tb_step.hip", "row_update.hpp", "noise.hpp"],
+    "tbp": ["tbp_step.hpp", "tbp_step.hip", "tb_step.hpp", "row_update.hpp", "noise.hpp"],
     "dense": ["dense.hpp", "dense_f32.hip", "dense_f64.hip", "row_update.hpp", "noise.hpp"],
 }
 
@@ -186,6 +187,10 @@ def unit_of(kernel_name: str):
     rocprofv3's names up to the last template argument the description fixes
     (the trailing flags select optional estimators)."""
     import re
+    m = re.search(r"tbp_step_kernel<(\w+),NS=(\d+),KT=(\d+)>", kernel_name)
+    if m:
+        real, ns, kt = m.group(1), m.group(2), int(m.group(3))
+        return "tbp", [f"tbp_step_kernel<{real}, {ns}, {kt},", f"tb_pairs_kernel<{real}, 4, {kt}>"], kt
     m = re.search(r"tb_step_kernel<(\w+),NS=(\d+),RPT=4,KT=(\d+)>", kernel_name)
     if m:
         real, ns, kt = m.group(1), m.group(2), int(m.group(3))
@@ -516,7 +521,7 @@ def main():
            "frac": alu_ops / per_unit_s / 1e9 / ALU_PEAK_GOPS}
     if dense:
         abytes, flops = dense_roofline(M, g.ns, R, len(pairs), prec, per_unit_s)
-    elif kind == "tb":
+    elif kind in ("tb", "tbp"):
         abytes = algorithmic_bytes(M, g.ns, R, len(pairs), prec, steps_per_launch=unit_steps)
     else:
         abytes = algorithmic_bytes(M, g.ns, R, len(pairs), prec, coded="CODED=1" in sol.kernel_name)
@@ -525,8 +530,9 @@ def main():
            "frac": achieved / HBM_PEAK_GBS, "traffic": traffic}
     unit_desc = {"csr": "one step (one step-kernel launch)",
                  "tb": f"one blocked launch = {unit_steps} steps (step kernel + pair kernel)",
+                 "tbp": f"one blocked launch = {unit_steps} steps (persistent step kernel + pair kernel)",
                  "dense": "one step (GEMM + epilogue launches)"}.get(kind, "one step")
-    if kind == "tb":
+    if kind in ("tb", "tbp"):
         # several steps per launch with the state in registers and LDS: VALU-limited
         roof = {"bound": "alu", **{k: alu[k] for k in ("achieved", "peak", "unit", "frac")}, "traffic": traffic,
                 "hbm": {k: hbm[k] for k in ("achieved", "peak", "unit", "frac")}}

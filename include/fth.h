@@ -144,6 +144,11 @@ typedef struct {
     int32_t acc_pp;          /* != 0: also accumulate <p_i p_j> (the momentum form of Eq. 7:
                                 p_n sampled with q_n) for the same pairs and diagonal; the
                                 estimates then come in two blocks, q-q then p-p */
+    int32_t temporal_persistent; /* blocked launches (temporal_steps > 0 or chosen by the autotuner):
+                                0: the persistent form when its LDS staging fits the device (one
+                                workgroup per resident slot walks a range of row tiles while the
+                                next tile's state streams into LDS); -1: one workgroup per tile.
+                                Results are identical either way. */
     int32_t acc_trace;       /* != 0: also the trace estimators of Sec. I, appended after the
                                 pair blocks: sum_i <q_i^2> (Tr of the position response),
                                 <q^T M q> (= -<q . F>, Tr[M g(M)]) and, with acc_pp,

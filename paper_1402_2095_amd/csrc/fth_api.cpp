@@ -628,6 +628,36 @@ bool tb_eligible(const fth_ctx* c, int KT, int block) {
     return T >= 1 && 2 * T >= E;
 }
 
+// Selects the blocked launch shape (KT steps, `block` threads) and, unless
+// the caller asked for one workgroup per tile, the persistent form when its
+// LDS staging fits the device (building the slot form of the rows once).
+fth_status tb_select(fth_ctx* c, int KT, int block) {
+    c->tb_kt = KT;
+    c->tb_block = block;
+    c->tbp_grid = 0;
+    if (c->opt.temporal_persistent != 0) return FTH_OK;
+    const bool f64 = c->prec == FTH_FP64;
+    const bool xtra = c->opt.acc_pp || c->opt.acc_trace;
+    const int E = block / (c->R / 4);
+    const int T = E - 2 * KT * int(c->band_w);
+    const size_t lds = fth::tbp_lds_bytes(f64, c->ns, block, c->R, T, c->opt.acc_trace != 0, xtra);
+    const int grid = f64 ? fth::tbp_resident_grid<double>(c->ns, KT, xtra, block, lds)
+                         : fth::tbp_resident_grid<float>(c->ns, KT, xtra, block, lds);
+    (void)hipGetLastError();  // an unsupported shape query leaves no sticky error behind
+    if (grid <= 0) return FTH_OK;
+    if (!c->d_tb_slots) {
+        const size_t sb = f64 ? sizeof(fth::TbSlotRow<double>) : sizeof(fth::TbSlotRow<float>);
+        HIP_OK(c->dalloc(&c->d_tb_slots, sb * size_t(c->n)));
+        const int rc = f64 ? fth::launch_tb_slots<double>(c->d_row_ptr, c->d_col, static_cast<const double*>(c->d_val),
+                                                          c->n, c->d_tb_slots, c->stream)
+                           : fth::launch_tb_slots<float>(c->d_row_ptr, c->d_col, static_cast<const float*>(c->d_val),
+                                                         c->n, c->d_tb_slots, c->stream);
+        if (rc != 0) return fail(FTH_EDEVICE, "slot-form build launch failed");
+    }
+    c->tbp_grid = grid;
+    return FTH_OK;
+}
+
 fth_status tb_prepare(fth_ctx* c) {
     if (c->d_snap || c->d_pair_slot) return FTH_OK;
     const size_t rb = c->real_bytes();
@@ -656,8 +686,10 @@ void tb_release(fth_ctx* c) {
     c->dfree(reinterpret_cast<void*&>(c->d_pair_slot));
     c->dfree(reinterpret_cast<void*&>(c->d_pair_slots));
     c->dfree(c->d_snap);
+    c->dfree(c->d_tb_slots);
     c->tb_nslots = 0;
     c->tb_kt = 0;
+    c->tbp_grid = 0;
 }
 
 // Blocked launch j of a chunk: steps [j KT, j KT + KT) of it.
@@ -675,7 +707,14 @@ fth_status enqueue_tb(fth_ctx* c, int j) {
     a.row_tiles = (c->n + tb.T - 1) / tb.T;
     a.row_tiles_padded = (a.row_tiles + 7) / 8 * 8;
     const fth::StepLaunch L = step_launch(c);
-    int rc = fth::launch_tb_step<Real>(a, tb, L, c->tb_kt, j * c->tb_kt, c->stream);
+    int rc;
+    if (c->tbp_grid > 0) {
+        tb.slots = c->d_tb_slots;
+        tb.grid = int32_t(std::min<int64_t>(c->tbp_grid, a.row_tiles));
+        rc = fth::launch_tbp_step<Real>(a, tb, L, c->tb_kt, j * c->tb_kt, c->stream);
+    } else {
+        rc = fth::launch_tb_step<Real>(a, tb, L, c->tb_kt, j * c->tb_kt, c->stream);
+    }
     if (rc == 0) rc = fth::launch_tb_pairs<Real>(a, tb, L, c->tb_kt, j * c->tb_kt, c->stream);
     if (rc == -2) return fail(FTH_EUNSUPPORTED, "no blocked kernel for ns=%d, KT=%d", c->ns, c->tb_kt);
     if (rc != 0) return fail(FTH_EDEVICE, "blocked step launch failed (%d): %s", rc, hipGetErrorString(hipGetLastError()));
@@ -785,9 +824,9 @@ fth_status autotune(fth_ctx* c) {
         c->nt = hit->second.nt;
         c->tuned_us = hit->second.us;
         if (hit->second.tb_kt > 0) {
-            c->tb_kt = hit->second.tb_kt;
-            c->tb_block = hit->second.tb_block;
-            return tb_prepare(c);
+            fth_status st = tb_prepare(c);
+            if (st != FTH_OK) return st;
+            return tb_select(c, hit->second.tb_kt, hit->second.tb_block);
         }
         return FTH_OK;
     }
@@ -835,8 +874,8 @@ fth_status autotune(fth_ctx* c) {
         for (int kt : kts)
             for (int tbb : tbs) {
                 if (!tb_eligible(c, kt, tbb)) continue;
-                c->tb_kt = kt;
-                c->tb_block = tbb;
+                st = tb_select(c, kt, tbb);
+                if (st != FTH_OK) return st;
                 double us = 0.0;
                 st = time_chunk(c, 2 * kt, &us);
                 if (st != FTH_OK) return st;
@@ -853,9 +892,13 @@ fth_status autotune(fth_ctx* c) {
     c->rpt = best.rpt;
     c->nt = best.nt;
     c->tuned_us = best.us;
-    c->tb_kt = best.tb_kt;
-    c->tb_block = best.tb_kt > 0 ? best.tb_block : 1024;
-    if (best.tb_kt == 0) tb_release(c);
+    if (best.tb_kt > 0) {
+        fth_status st2 = tb_select(c, best.tb_kt, best.tb_block);
+        if (st2 != FTH_OK) return st2;
+    } else {
+        tb_release(c);
+        c->tb_block = 1024;
+    }
     if (c->gexec) {
         (void)hipGraphExecDestroy(c->gexec);
         c->gexec = nullptr;
@@ -1001,6 +1044,8 @@ fth_status fth_create(const fth_matrix* M_in, const fth_gle* gle_in, double dt, 
         opt.temporal_threads != 1024)
         return fail(FTH_EINVAL, "temporal_threads must be 0, 256, 512 or 1024");
     if (opt.coded_matrix != 0 && opt.coded_matrix != -1) return fail(FTH_EINVAL, "coded_matrix must be 0 or -1");
+    if (opt.temporal_persistent != 0 && opt.temporal_persistent != -1)
+        return fail(FTH_EINVAL, "temporal_persistent must be 0 or -1");
     if (opt.acc_pp != 0 && opt.acc_pp != 1) return fail(FTH_EINVAL, "acc_pp must be 0 or 1");
     if (opt.acc_trace != 0 && opt.acc_trace != 1) return fail(FTH_EINVAL, "acc_trace must be 0 or 1");
     if (npairs < 0 || (npairs > 0 && !pairs)) return fail(FTH_EINVAL, "invalid pair list");
@@ -1122,10 +1167,10 @@ fth_status fth_run(fth_ctx* c, int64_t nsteps, int32_t replicas) {
                         "temporal blocking needs CSR with half-bandwidth <= %lld (%lld), <= 8 entries per row (%d), "
                         "4 <= R <= 256 and at least half of each workgroup's rows as output",
                         (long long)kTbMaxW, (long long)c->band_w, c->max_row_nnz);
-        c->tb_kt = c->opt.temporal_steps;
-        c->tb_block = tbb;
         c->rpt = 4;
         st = tb_prepare(c);
+        if (st != FTH_OK) return st;
+        st = tb_select(c, c->opt.temporal_steps, tbb);
         if (st != FTH_OK) return st;
     }
     if (c->opt.tune && !c->tuned) {
@@ -1334,6 +1379,11 @@ fth_status fth_kernel_name(const fth_ctx* c, char* name, size_t len) {
         std::snprintf(name, len, "%s<RT=%d,ksplit=%d> + dense_epilogue_kernel<%s,NS=%d,RPT=%d,NT=%d>",
                       c->prec == FTH_FP64 ? "gemm_f64_kernel" : "gemm_bf16x3_kernel", c->R / 16, c->ksplit,
                       c->prec == FTH_FP64 ? "double" : "float", c->ns, c->rpt, int(c->nt));
+    else if (c->tb_kt > 0 && c->tbp_grid > 0)
+        std::snprintf(name, len,
+                      "tbp_step_kernel<%s,NS=%d,KT=%d> block=%d grid=%d (persistent; + csr_step_kernel block=%d tail)%s",
+                      c->prec == FTH_FP64 ? "double" : "float", c->ns, c->tb_kt, c->tb_block, c->tbp_grid, c->block,
+                      c->tuned ? " (autotuned)" : "");
     else if (c->tb_kt > 0)
         std::snprintf(name, len, "tb_step_kernel<%s,NS=%d,RPT=4,KT=%d> block=%d (+ csr_step_kernel block=%d tail)%s",
                       c->prec == FTH_FP64 ? "double" : "float", c->ns, c->tb_kt, c->tb_block, c->block,

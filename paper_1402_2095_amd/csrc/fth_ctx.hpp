@@ -72,6 +72,8 @@ struct fth_ctx {
     int32_t* d_pair_slots = nullptr;   // [npairs][2]
     void* d_snap = nullptr;            // [kTbMaxSteps][2][nslots][R]
     int64_t tb_nslots = 0;
+    void* d_tb_slots = nullptr;        // slot form of the rows (TbSlotRow) for the persistent form
+    int tbp_grid = 0;                  // workgroups of the persistent blocked step, 0: one per tile
     // schedule
     int R = 0;
     int rpt = 0;

@@ -138,7 +138,46 @@ struct TbArgs {
     Real* snap;                // [KT][2][nslots][R]: q (and p, if kept) of pair rows at each step
     int64_t nslots;
     const int32_t* pair_slots; // [npairs][2]: snapshot slots of each pair's rows
+    // persistent form: the slot form of the rows (TbSlotRow<Real>[N], null: the
+    // one-launch-per-tile form) and the workgroups of the persistent grid
+    const void* slots;
+    int32_t grid;
 };
+
+// Slot form of a CSR row of at most 8 entries for the persistent blocked
+// step: values in stored order (unused slots 0), column offsets j - i as
+// signed bytes, the entry count; a whole number of 16-byte chunks, so a wave
+// stages its rows with 16-byte direct-to-LDS loads.
+template <typename Real>
+struct TbSlotRow {
+    Real val[8];
+    int8_t off[8];
+    int32_t nz;
+    int32_t pad;
+};
+static_assert(sizeof(TbSlotRow<float>) % 16 == 0 && sizeof(TbSlotRow<double>) % 16 == 0, "slot rows are 16-byte chunks");
+
+// Bookkeeping words a wave stages per tile with 4-byte direct-to-LDS loads
+// (256 bytes each): the diagonal block sum (two words), the pair snapshot
+// slot and, with momentum-form accumulators, their block sum (two words).
+constexpr int tbp_aux_words(bool xtra) { return xtra ? 5 : 3; }
+
+// LDS bytes of the persistent blocked step for a workgroup of `block`
+// threads (4 replicas per thread): q of the extended rows twice, the trace
+// row sums (if kept) and each wave's staging area (state, slot rows and
+// bookkeeping of the next tile).
+constexpr size_t tbp_lds_bytes(bool f64, int ns, int block, int R, int T, bool traces, bool xtra) {
+    const size_t rb = f64 ? 8 : 4;
+    const size_t E = size_t(block) * 4 / size_t(R);
+    const size_t q = 2 * E * size_t(R) * rb;
+    const size_t tr = traces ? 2 * size_t(T) * 3 * 8 : 0;
+    const size_t vi = 4 * rb / 16;                       // 16-byte loads per 4-replica vector
+    const size_t rows_per_wave = 64 / (size_t(R) / 4);
+    const size_t sb = f64 ? sizeof(TbSlotRow<double>) : sizeof(TbSlotRow<float>);
+    const size_t ci = (rows_per_wave * sb + 1023) / 1024;  // slot-row loads per wave
+    const size_t stage = (size_t(block) / 64) * ((size_t(ns + 2) * vi + ci) * 1024 + size_t(tbp_aux_words(xtra)) * 256);
+    return q + tr + stage;
+}
 
 // One entry of the packed multi-request work list.
 struct PackedTile {
@@ -170,6 +209,17 @@ template <typename Real>
 int launch_tb_step(const StepArgs<Real>& a, const TbArgs<Real>& tb, const StepLaunch& L, int KT, int k, void* stream);
 template <typename Real>
 int launch_tb_pairs(const StepArgs<Real>& a, const TbArgs<Real>& tb, const StepLaunch& L, int KT, int k, void* stream);
+// Persistent form of the blocked step (tb.slots and tb.grid set): one
+// workgroup per slot of the grid walks a contiguous range of row tiles.
+template <typename Real>
+int launch_tbp_step(const StepArgs<Real>& a, const TbArgs<Real>& tb, const StepLaunch& L, int KT, int k, void* stream);
+// Workgroups of the persistent blocked step that fit on the device at once
+// (0 if the shape does not fit); lds = tbp_lds_bytes of the shape.
+template <typename Real>
+int tbp_resident_grid(int ns, int KT, bool xtra, int block, size_t lds);
+// Slot form of CSR rows (at most 8 entries each) for the persistent blocked step.
+template <typename Real>
+int launch_tb_slots(const int64_t* row_ptr, const int32_t* col, const Real* val, int64_t N, void* out, void* stream);
 int launch_packed_csr(const StepArgs<float>* table, const PackedTile* tiles, const int32_t* ntiles, int ns, bool nt,
                       int grid, int k, void* stream);
 int launch_advance_all(const StepArgs<float>* table, const int32_t* nslots, int64_t K, void* stream);

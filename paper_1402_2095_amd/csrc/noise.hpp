@@ -32,8 +32,9 @@ __device__ __forceinline__ Block4 philox4x32_10(uint32_t c0, uint32_t c1, uint32
     for (int round = 0; round < 10; ++round) {
         const uint64_t pa = uint64_t(kMulA) * c0;
         const uint64_t pb = uint64_t(kMulB) * c2;
-        const uint32_t x0 = uint32_t(pb >> 32) ^ c1 ^ k0;
-        const uint32_t x2 = uint32_t(pa >> 32) ^ c3 ^ k1;
+        // three-way XOR in one v_bitop3_b32 (truth table 0x96)
+        const uint32_t x0 = __builtin_amdgcn_bitop3_b32(uint32_t(pb >> 32), c1, k0, 0x96);
+        const uint32_t x2 = __builtin_amdgcn_bitop3_b32(uint32_t(pa >> 32), c3, k1, 0x96);
         c1 = uint32_t(pb);
         c3 = uint32_t(pa);
         c0 = x0;
@@ -44,12 +45,19 @@ __device__ __forceinline__ Block4 philox4x32_10(uint32_t c0, uint32_t c1, uint32
     return Block4{{c0, c1, c2, c3}};
 }
 
+// u = (2 (x >> 9) + 1) 2^-24 in FP32 without a conversion: the top 23 bits
+// as the mantissa of a float in [1, 2) give 1 + (x >> 9) 2^-23, and
+// subtracting 1 - 2^-24 is exact (Sterbenz: both operands lie in [1/2, 2]).
+__device__ __forceinline__ float uniform_f32(uint32_t x) {
+    return __uint_as_float((x >> 9) | 0x3f800000u) - 0x1.fffffep-1f;
+}
+
 // Box-Muller in FP32 with the hardware transcendental unit: v_log_f32 is
 // log2, v_sin_f32 / v_cos_f32 take their argument in revolutions, so
 // sin(2 pi u) needs no multiply.
 __device__ __forceinline__ void box_muller(uint32_t a, uint32_t b, float& zc, float& zs) {
-    const float ua = __builtin_fmaf(float(a >> 9), 0x1p-23f, 0x1p-24f);
-    const float ub = __builtin_fmaf(float(b >> 9), 0x1p-23f, 0x1p-24f);
+    const float ua = uniform_f32(a);
+    const float ub = uniform_f32(b);
     const float l2 = __builtin_amdgcn_logf(ua);                      // log2(ua) < 0
     const float rad = __builtin_amdgcn_sqrtf(-1.3862943611198906f * l2);  // sqrt(-2 ln ua)
     zc = rad * __builtin_amdgcn_cosf(ub);

@@ -57,7 +57,8 @@ class fth_options(ctypes.Structure):
                 ("replicas", ctypes.c_int32), ("hip_stream", ctypes.c_void_p),
                 ("steps_per_graph", ctypes.c_int32), ("tune", ctypes.c_int32),
                 ("temporal_steps", ctypes.c_int32), ("temporal_threads", ctypes.c_int32),
-                ("coded_matrix", ctypes.c_int32), ("acc_pp", ctypes.c_int32), ("acc_trace", ctypes.c_int32),
+                ("coded_matrix", ctypes.c_int32), ("acc_pp", ctypes.c_int32),
+                ("temporal_persistent", ctypes.c_int32), ("acc_trace", ctypes.c_int32),
                 ("scale_r", ctypes.c_double), ("scale_m", ctypes.c_double), ("gle_alpha", ctypes.c_double),
                 ("gle_gamma", ctypes.c_double), ("allocator", ctypes.c_void_p)]
 
@@ -368,7 +369,8 @@ class Solver:
 
     def __init__(self, M, A_p, C_p, dt, pairs=None, replicas=0, precision=FTH_FP32, seed=0, stream_id=0,
                  burn_in=0, block_len=100, acc_diag=False, steps_per_graph=0, hip_stream=None, tune=False,
-                 temporal_steps=0, temporal_threads=0, coded_matrix=0, acc_pp=False, acc_trace=False,
+                 temporal_steps=0, temporal_threads=0, temporal_persistent=0, coded_matrix=0, acc_pp=False,
+                 acc_trace=False,
                  scale_r=1.0, scale_m=0.0, gle_alpha=1.0, gle_gamma=1.0, allocator=None):
         self.n = int(M.shape[0] if isinstance(M, np.ndarray) else M.n)
         self.ns = int(np.asarray(A_p).shape[0] - 1)
@@ -377,6 +379,7 @@ class Solver:
                                   block_len=block_len, acc_diag=int(acc_diag), replicas=int(replicas),
                                   steps_per_graph=steps_per_graph, tune=int(tune),
                                   temporal_steps=int(temporal_steps), temporal_threads=int(temporal_threads),
+                                  temporal_persistent=int(temporal_persistent),
                                   coded_matrix=int(coded_matrix), acc_pp=int(acc_pp), acc_trace=int(acc_trace),
                                   scale_r=float(scale_r), scale_m=float(scale_m), gle_alpha=float(gle_alpha),
                                   gle_gamma=float(gle_gamma))

@@ -93,7 +93,7 @@ def test_small_momentum_parity(R, prec):
 def test_blocked_momentum_and_traces_parity(kt):
     M = fi.banded_spd_csr(3001, 19, dtype=np.float64)
     run_parity(M, fi.dt_rule(fi.gershgorin_max(M)), fi.load_gle("fermi_b20_ns4"), 32, fth.FTH_FP64,
-               fi.random_pairs(M.n, 40, 18), f"blocked KT={kt}", "tb_step_kernel", temporal_steps=kt)
+               fi.random_pairs(M.n, 40, 18), f"blocked KT={kt}", f"KT={kt}", temporal_steps=kt)
 
 
 @pytest.mark.parametrize("kt", [3, 5])
@@ -105,7 +105,7 @@ def test_blocked_momentum_bit_identical(kt):
               block_len=4, steps_per_graph=10)
     a = fth.Solver(M, g.A_p, g.C_p, h, temporal_steps=kt, **kw).run(1).run(44)
     b = fth.Solver(M, g.A_p, g.C_p, h, temporal_steps=-1, **kw).run(1).run(44)
-    assert "tb_step_kernel" in a.kernel_name
+    assert "tb_step_kernel" in a.kernel_name or "tbp_step_kernel" in a.kernel_name
     for x, y in zip(a.state(), b.state()):
         assert np.array_equal(x, y)
     for x, y in zip(a.accumulators()[:3], b.accumulators()[:3]):

@@ -22,10 +22,11 @@ def banded(n, seed, prec):
     return M, fi.dt_rule(fi.gershgorin_max(M))
 
 
-def run_pair(M, h, g, kt, threads, R, prec, chunks, steps_per_graph, npairs=64):
+def run_pair(M, h, g, kt, threads, R, prec, chunks, steps_per_graph, npairs=64, persistent=0):
     kw = dict(pairs=fi.random_pairs(M.n, npairs, 5) if npairs else None, replicas=R, precision=prec, seed=11,
               stream_id=2, burn_in=4, block_len=7, acc_diag=True, steps_per_graph=steps_per_graph)
-    a = fth.Solver(M, g.A_p, g.C_p, h, temporal_steps=kt, temporal_threads=threads, **kw)
+    a = fth.Solver(M, g.A_p, g.C_p, h, temporal_steps=kt, temporal_threads=threads, temporal_persistent=persistent,
+                   **kw)
     b = fth.Solver(M, g.A_p, g.C_p, h, temporal_steps=-1, **kw)
     for k in chunks:
         a.run(k)
@@ -44,16 +45,21 @@ def assert_identical(a, b, label):
 # (KT, threads, R): every combination keeps at least half of a workgroup's rows as output
 @pytest.mark.parametrize("kt,threads,R", [(3, 256, 16), (3, 512, 32), (3, 1024, 32), (5, 1024, 32), (5, 512, 8)])
 @pytest.mark.parametrize("prec", [fth.FTH_FP32, fth.FTH_FP64], ids=["fp32", "fp64"])
-def test_blocked_bit_identical_to_one_step(kt, threads, R, prec):
+@pytest.mark.parametrize("persistent", [0, -1], ids=["persistent", "per-tile"])
+def test_blocked_bit_identical_to_one_step(kt, threads, R, prec, persistent):
+    """Both blocked forms (the persistent one, which stages the next tile in
+    LDS, and one workgroup per tile) reproduce the one-step kernel bit for
+    bit."""
     if prec == fth.FTH_FP64 and threads > 512:
         threads = 512   # FP64 with ns = 4 keeps (p, s) in the registers of at most 512 threads
     g = fi.load_gle("fermi_b20_ns4")
     M, h = banded(30011, 7, prec)   # ragged: no tile size divides n
     # chunks: shorter than a launch pair, a graph length that is not a multiple of 2 KT, a long run
-    a, b = run_pair(M, h, g, kt, threads, R, prec, chunks=(1, 2 * kt - 1, 37, 100), steps_per_graph=16)
+    a, b = run_pair(M, h, g, kt, threads, R, prec, chunks=(1, 2 * kt - 1, 37, 100), steps_per_graph=16,
+                    persistent=persistent)
     print(f"[tb] {a.kernel_name}", flush=True)
-    assert "tb_step_kernel" in a.kernel_name
-    assert_identical(a, b, (kt, threads, prec))
+    assert ("tbp_step_kernel" if persistent == 0 else "tb_step_kernel") in a.kernel_name
+    assert_identical(a, b, (kt, threads, prec, persistent))
 
 
 @pytest.mark.parametrize("R", [4, 8, 64])
@@ -122,7 +128,8 @@ def test_autotuner_may_block_and_keeps_trajectory():
         assert np.allclose(x, y, rtol=1e-12, atol=0)
 
 
-def test_blocked_full_size_bit_identical():
+@pytest.mark.parametrize("persistent", [0, -1], ids=["persistent", "per-tile"])
+def test_blocked_full_size_bit_identical(persistent):
     """Banded N = 1e6, R = 32 in the launch shape the benchmark's autotuner
     picks (KT = 5, 1024 threads): bit-identical to the one-step kernel."""
     g = fi.load_gle("fermi_b20_ns4")
@@ -130,9 +137,12 @@ def test_blocked_full_size_bit_identical():
     h = fi.dt_rule(fi.gershgorin_max(M))
     kw = dict(pairs=fi.random_pairs(M.n, 1024, 3004), replicas=32, seed=2, acc_diag=True, block_len=4,
               steps_per_graph=10)
-    a = fth.Solver(M, g.A_p, g.C_p, h, temporal_steps=5, temporal_threads=1024, **kw).run(20)
+    a = fth.Solver(M, g.A_p, g.C_p, h, temporal_steps=5, temporal_threads=1024, temporal_persistent=persistent,
+                   **kw).run(20)
     b = fth.Solver(M, g.A_p, g.C_p, h, temporal_steps=-1, **kw).run(20)
+    print(f"[tb] {a.kernel_name}", flush=True)
     assert "KT=5" in a.kernel_name and "block=1024" in a.kernel_name
+    assert ("tbp_step_kernel" if persistent == 0 else "tb_step_kernel") in a.kernel_name
     for x, y in zip(a.state(), b.state()):
         assert np.array_equal(x, y)
     for x, y in zip(a.accumulators()[:3], b.accumulators()[:3]):
