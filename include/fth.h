@@ -188,9 +188,17 @@ fth_status fth_create(const fth_matrix* M, const fth_gle* gle, double dt,
  * replicas (cumulative: continues from the previous call).  The first call
  * fixes R (replicas == 0 uses opt.replicas); a later call with another
  * non-zero R returns FTH_ESTATE.  R must be a power of two <= 512 for the
- * sparse kernels.  Returns FTH_ENONFINITE (and poisons the context) if any
- * state value became non-finite; FTH_ESTATE on a poisoned context. */
+ * sparse kernels.  The first call also runs the autotuner when opt.tune is
+ * set, so nsteps == 0 fixes R and the launch shape without advancing.
+ * Returns FTH_ENONFINITE (and poisons the context) if any state value
+ * became non-finite; FTH_ESTATE on a poisoned context. */
 fth_status fth_run(fth_ctx* ctx, int64_t nsteps, int32_t replicas);
+
+/* Change the number of steps captured per hipGraph launch (0: default) and
+ * drop the current graph; the next fth_run captures one of the new length.
+ * A blocked schedule rounds it down to whole blocked launches (at least
+ * one).  Errors: FTH_EINVAL. */
+fth_status fth_set_steps_per_graph(fth_ctx* ctx, int32_t steps);
 
 /* Number of estimates: npairs, plus n when acc_diag (pairs first, in input
  * order, then the diagonal in index order); twice that with acc_pp, the q-q
@@ -305,25 +313,43 @@ size_t fth_footprint_bytes(const fth_matrix* M, int32_t ns, int32_t replicas,
 /* ------------------------------------------------------------------ */
 /* Serving layer: a request loop over many solves that share one GPU.   */
 /* ------------------------------------------------------------------ */
-/* Requests arrive at any time (fth_server_submit).  Each fth_server_tick
- * admits queued requests in arrival order while their device footprint
- * (fth_footprint_bytes) fits the remaining HBM budget, advances every
- * running request by steps_per_tick steps, reads their stderr summaries and
- * retires the ones that reached their target (or max_steps), freeing their
- * memory for the queue.  Sparse FP32 requests with the same ns are packed
- * into one persistent kernel per step (a device work list of row and pair
- * tiles, captured as one hipGraph per tick), so work of concurrent requests
- * of uneven size overlaps on the device; dense and FP64 requests run their
- * own kernels in the same tick.  A request's trajectory depends only on its
- * own inputs (matrix, GLE, dt, seed, stream_id), not on what runs beside it.
- * A server is not thread-safe. */
+/* Requests arrive at any time (fth_server_submit).  Independent
+ * simulations of one GPU run concurrently (the paper's remark, Sec. III,
+ * that replicas and solves are trivially parallel):
+ *  - admission: queued requests get a context (device memory) in arrival
+ *    order while their footprint (fth_footprint_bytes) fits the remaining
+ *    HBM budget and fewer than max_active run;
+ *  - work is issued in chunks, each on its own stream: a running request
+ *    that is not packed advances alone on its context's stream; sparse FP32
+ *    requests with the same ns are packed into one persistent kernel per step
+ *    (a device work list of row and pair tiles of all members, one captured
+ *    hipGraph per chunk length) on the group's stream; dense and FP64
+ *    requests run their own GEMM and step kernels.  Chunks of different
+ *    requests and groups overlap on the device;
+ *  - a chunk never crosses a check boundary (a multiple of steps_per_tick
+ *    steps of that request) and is shortened (to a divisor of
+ *    steps_per_tick) when the previous chunk's measured time says it would
+ *    take longer than quantum_ms, so a new arrival waits for the first chunk
+ *    that ends, not for the slowest request;
+ *  - a new request starts unpacked and joins its packed group at its next
+ *    check boundary once the group is also at one;
+ *  - at each check boundary the request's estimates and block stderrs are
+ *    read (a few KB); it retires at its target (or max_steps), releasing its
+ *    memory for the queue.
+ * A request's trajectory depends only on its own inputs (matrix, GLE, dt,
+ * seed, stream_id, spectral map), and it stops at a check boundary, so its
+ * result is the same alone and in any mix.  A server is not thread-safe. */
 typedef struct fth_server fth_server;
 
 typedef struct {
     size_t hbm_budget;       /* bytes of device memory for requests; 0: 80% of free */
-    int32_t steps_per_tick;  /* steps per tick (and between stderr checks); 0: 200 */
+    int32_t steps_per_tick;  /* steps between stderr checks (the chunk length
+                                at most); 0: 200 */
     int32_t max_active;      /* running requests at most; 0: 64 */
     int32_t min_blocks;      /* complete blocks needed before a stderr counts; 0: 8 */
+    double quantum_ms;       /* target device time of one chunk (chunks are cut to
+                                divisors of steps_per_tick to stay under it);
+                                0: 20 ms, < 0: never cut */
 } fth_server_options;
 
 typedef struct {
@@ -341,8 +367,16 @@ typedef struct {
     double target_rel_stderr;/* stop when every estimate's stderr / scale <= target;
                                 scale = sqrt(est_ii est_jj) when both diagonals are
                                 among the request's pairs, else |est| */
-    int64_t max_steps;       /* stop at the first tick boundary at or after this many
-                                steps (0: no limit); requests advance in whole ticks */
+    int64_t max_steps;       /* stop at the first check boundary at or after this many
+                                steps (0: no limit) */
+    /* Spectral map of Sec. I for this request (as in fth_options: the
+       dynamics run on M' = scale_r M + scale_m I with (gle_alpha A_p,
+       gle_gamma C_p); 0 for scale_r, gle_alpha, gle_gamma means 1), so one
+       fitted GLE serves requests of any spectrum.  unscale_target (an
+       fth_target, or -1) maps the results back to f(M) with fth_unscale
+       (pairs (i, i) count as diagonal entries); -1 returns them as run. */
+    double scale_r, scale_m, gle_alpha, gle_gamma;
+    int32_t unscale_target;
 } fth_request;
 
 typedef enum {
@@ -358,8 +392,15 @@ typedef struct {
     double t_submit, t_start, t_finish;  /* seconds on the server's clock (-1: not yet) */
     int64_t n_out;           /* number of estimates (= npairs) */
     int32_t replicas;
-    int32_t packed;          /* 1 if run by the packed multi-request kernel */
+    int32_t packed;          /* 1 once run by the packed multi-request kernel */
     size_t footprint;        /* device bytes reserved while running */
+    double device_ms;        /* device time of the chunks that advanced it (HIP events
+                                around each chunk on its stream; a packed chunk counts
+                                for every member) */
+    int64_t chunks;          /* chunks that advanced it */
+    double device_first_ms;  /* device clock (ms since the server was created, from HIP events):
+                                start of its first chunk and end of its last (-1: none yet) */
+    double device_last_ms;
 } fth_request_info;
 
 /* Create a server on the current device.  opt may be NULL (defaults). */
@@ -367,7 +408,11 @@ fth_status fth_server_create(const fth_server_options* opt, fth_server** out);
 /* Queue a request; *id receives its id (>= 1).  FTH_EINVAL on invalid input,
  * FTH_ENOMEM if its footprint exceeds the whole budget. */
 fth_status fth_server_submit(fth_server* srv, const fth_request* req, uint64_t* id);
-/* Admit, run one tick of steps for every running request, check, retire. */
+/* One round of the loop: retire finished chunks (check, retire), admit,
+ * issue a chunk to every idle request and packed group, then wait until at
+ * least one issued chunk has finished and process it.  Returns at once when
+ * nothing is running.  A request that fails (at admission or in a chunk)
+ * is marked FTH_REQ_FAILED with its status; the others go on. */
 fth_status fth_server_tick(fth_server* srv);
 /* State of a request (any state). */
 fth_status fth_server_poll(fth_server* srv, uint64_t id, fth_request_info* info);

@@ -910,7 +910,7 @@ fth_status autotune(fth_ctx* c) {
 fth_status run_enqueue(fth_ctx* c, int64_t nsteps) {
     fth_status st;
     int K = c->opt.steps_per_graph > 0 ? c->opt.steps_per_graph : kDefaultGraphSteps;
-    if (c->tb_kt > 0) K = (K + c->tb_kt - 1) / c->tb_kt * c->tb_kt;  // whole blocked launches
+    if (c->tb_kt > 0) K = std::max(1, K / c->tb_kt) * c->tb_kt;  // whole blocked launches
     st = trace_prepare(c, c->small ? 4096 : K);
     if (st != FTH_OK) return st;
     if (c->d_qt && c->qt_dirty) {
@@ -1156,7 +1156,6 @@ fth_status fth_run(fth_ctx* c, int64_t nsteps, int32_t replicas) {
     if (c->step + nsteps >= (int64_t(1) << 32)) return fail(FTH_EINVAL, "total steps must stay below 2^32");
     fth_status st = ensure_state(c, replicas);
     if (st != FTH_OK) return st;
-    if (nsteps == 0) return FTH_OK;
     HIP_OK(hipSetDevice(c->device));
     if (c->opt.temporal_steps > 0 && c->tb_kt == 0) {
         const int tbb = c->opt.temporal_threads > 0
@@ -1178,6 +1177,7 @@ fth_status fth_run(fth_ctx* c, int64_t nsteps, int32_t replicas) {
         if (st != FTH_OK) return st;
         c->tuned = true;
     }
+    if (nsteps == 0) return FTH_OK;  // shape fixed (and tuned): nothing to run
     if (c->opt.hip_stream) {
         // order after the caller's stream
         HIP_OK(hipEventRecord(c->ev0, static_cast<hipStream_t>(c->opt.hip_stream)));
@@ -1192,6 +1192,17 @@ fth_status fth_run(fth_ctx* c, int64_t nsteps, int32_t replicas) {
     HIP_OK(hipEventElapsedTime(&ms, c->ev0, c->ev1));
     c->last_ms = ms;
     return run_complete(c, nsteps);
+}
+
+fth_status fth_set_steps_per_graph(fth_ctx* c, int32_t steps) {
+    if (!c || steps < 0) return fail(FTH_EINVAL, "invalid arguments");
+    if (c->gexec) {
+        HIP_OK(hipStreamSynchronize(c->stream));
+        (void)hipGraphExecDestroy(c->gexec);
+        c->gexec = nullptr;
+    }
+    c->opt.steps_per_graph = steps;
+    return FTH_OK;
 }
 
 int64_t fth_num_outputs(const fth_ctx* c) { return c ? c->n_out() : 0; }

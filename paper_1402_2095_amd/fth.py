@@ -30,6 +30,7 @@ EXPORTS = [
     "fth_server_create", "fth_server_submit", "fth_server_tick", "fth_server_poll", "fth_server_result",
     "fth_server_cancel", "fth_server_clock", "fth_server_stats", "fth_server_destroy",
     "fth_spectral_map", "fth_gershgorin", "fth_unscale", "fth_device_bytes", "fth_save", "fth_load",
+    "fth_set_steps_per_graph",
 ]
 FTH_TARGET_INVSQRT, FTH_TARGET_LN, FTH_TARGET_EXPNEG = 0, 1, 2
 FTH_REQ_QUEUED, FTH_REQ_RUNNING, FTH_REQ_DONE, FTH_REQ_FAILED, FTH_REQ_CANCELLED = 0, 1, 2, 3, 4
@@ -92,21 +93,25 @@ def torch_allocator():
 
 class fth_server_options(ctypes.Structure):
     _fields_ = [("hbm_budget", ctypes.c_size_t), ("steps_per_tick", ctypes.c_int32),
-                ("max_active", ctypes.c_int32), ("min_blocks", ctypes.c_int32)]
+                ("max_active", ctypes.c_int32), ("min_blocks", ctypes.c_int32), ("quantum_ms", ctypes.c_double)]
 
 
 class fth_request(ctypes.Structure):
     _fields_ = [("M", fth_matrix), ("gle", fth_gle), ("dt", ctypes.c_double), ("pairs", ctypes.c_void_p),
                 ("npairs", ctypes.c_int64), ("replicas", ctypes.c_int32), ("precision", ctypes.c_int32),
                 ("seed", ctypes.c_uint64), ("stream_id", ctypes.c_uint32), ("burn_in", ctypes.c_int64),
-                ("block_len", ctypes.c_int64), ("target_rel_stderr", ctypes.c_double), ("max_steps", ctypes.c_int64)]
+                ("block_len", ctypes.c_int64), ("target_rel_stderr", ctypes.c_double), ("max_steps", ctypes.c_int64),
+                ("scale_r", ctypes.c_double), ("scale_m", ctypes.c_double), ("gle_alpha", ctypes.c_double),
+                ("gle_gamma", ctypes.c_double), ("unscale_target", ctypes.c_int32)]
 
 
 class fth_request_info(ctypes.Structure):
     _fields_ = [("state", ctypes.c_int32), ("status", ctypes.c_int32), ("steps", ctypes.c_int64),
                 ("nblocks", ctypes.c_int64), ("max_rel_stderr", ctypes.c_double), ("t_submit", ctypes.c_double),
                 ("t_start", ctypes.c_double), ("t_finish", ctypes.c_double), ("n_out", ctypes.c_int64),
-                ("replicas", ctypes.c_int32), ("packed", ctypes.c_int32), ("footprint", ctypes.c_size_t)]
+                ("replicas", ctypes.c_int32), ("packed", ctypes.c_int32), ("footprint", ctypes.c_size_t),
+                ("device_ms", ctypes.c_double), ("chunks", ctypes.c_int64), ("device_first_ms", ctypes.c_double),
+                ("device_last_ms", ctypes.c_double)]
 
 
 _lib = None
@@ -139,6 +144,7 @@ def lib():
             "fth_version": (ctypes.c_char_p, []),
             "fth_noise_sample": (i32, [u64, ctypes.c_uint32, i64, P, P, P, P, i32, P, P]),
             "fth_force": (i32, [P, P, P]),
+            "fth_set_steps_per_graph": (i32, [P, i32]),
             "fth_server_create": (i32, [P, P]),
             "fth_server_submit": (i32, [P, P, P]),
             "fth_server_tick": (i32, [P]),
@@ -399,6 +405,10 @@ class Solver:
     def read(self):
         return fth_read(self.ctx)
 
+    def set_steps_per_graph(self, steps: int):
+        _check(lib().fth_set_steps_per_graph(self.ctx, int(steps)))
+        return self
+
     def accumulators(self):
         return fth_get_accumulators(self.ctx)
 
@@ -445,19 +455,21 @@ class Solver:
 class Server:
     """Request loop over many solves on one GPU (fth_server_*)."""
 
-    def __init__(self, hbm_budget=0, steps_per_tick=0, max_active=0, min_blocks=0):
-        o = fth_server_options(hbm_budget, steps_per_tick, max_active, min_blocks)
+    def __init__(self, hbm_budget=0, steps_per_tick=0, max_active=0, min_blocks=0, quantum_ms=0.0):
+        o = fth_server_options(hbm_budget, steps_per_tick, max_active, min_blocks, float(quantum_ms))
         h = ctypes.c_void_p()
         _check(lib().fth_server_create(ctypes.byref(o), ctypes.byref(h)))
         self.h = h
 
     def submit(self, M, A_p, C_p, dt, pairs, replicas=0, precision=FTH_FP32, seed=0, stream_id=0, burn_in=0,
-               block_len=0, target=1e-2, max_steps=0) -> int:
+               block_len=0, target=1e-2, max_steps=0, scale_r=1.0, scale_m=0.0, gle_alpha=1.0, gle_gamma=1.0,
+               unscale_target=-1) -> int:
         m = _Matrix(M)
         g, keep = _gle_struct(A_p, C_p)
         pr = np.ascontiguousarray(pairs, dtype=np.int32).reshape(-1, 2)
         q = fth_request(m.struct, g, float(dt), pr.ctypes.data, len(pr), int(replicas), int(precision), int(seed),
-                        int(stream_id), int(burn_in), int(block_len), float(target), int(max_steps))
+                        int(stream_id), int(burn_in), int(block_len), float(target), int(max_steps),
+                        float(scale_r), float(scale_m), float(gle_alpha), float(gle_gamma), int(unscale_target))
         rid = ctypes.c_uint64()
         _check(lib().fth_server_submit(self.h, ctypes.byref(q), ctypes.byref(rid)))
         return int(rid.value)

@@ -127,3 +127,118 @@ def test_cancel_releases_memory():
     assert srv.poll(rid)["state"] == fth.FTH_REQ_CANCELLED
     assert srv.stats() == (0, 0, 0)
     srv.tick()  # an empty tick is fine
+
+
+def normwise(a, b):
+    den = np.max(np.abs(b))
+    return float(np.max(np.abs(a - b)) / den) if den > 0 else float(np.max(np.abs(a)))
+
+
+def test_mix_against_oracle():
+    """One server running sparse FP32 requests of uneven size (packed), a
+    dense split-BF16x3 request and a sparse FP64 request side by side for
+    1000 steps: each request's estimates and block stderrs equal the FP64
+    oracle's for the same inputs, seed and noise stream, to the FP32 (1e-4)
+    or FP64 (1e-10) trajectory tolerance."""
+    import oracle
+    common = dict(block_len=50, max_steps=1000, target=0.0)
+    reqs = [("band2000", band_request(2000, 61, 31), fth.FTH_FP32, 32),
+            ("lap12", lap_request(12, 62, 32), fth.FTH_FP32, 32),
+            ("band5003", band_request(5003, 63, 33), fth.FTH_FP32, 32),
+            ("dense600", dense_request(600, 64, 34), fth.FTH_FP32_BF16X3, 64),
+            ("band3001-fp64", dict(band_request(3001, 65, 35), precision=fth.FTH_FP64), fth.FTH_FP64, 8)]
+    srv = fth.Server(steps_per_tick=100)
+    ids = []
+    for name, kw, prec, R in reqs:
+        kw = dict(kw)
+        kw.pop("precision", None)
+        ids.append(srv.submit(**kw, precision=prec, replicas=R, **common))
+    run_to_done(srv, ids)
+    for (name, kw, prec, R), rid in zip(reqs, ids):
+        info = srv.poll(rid)
+        assert info["state"] == fth.FTH_REQ_DONE and info["steps"] == 1000, (name, info)
+        est, se = srv.result(rid)
+        M = kw["M"]
+        M64 = M.astype(np.float64) if isinstance(M, np.ndarray) else fi.CSR(M.n, M.row_ptr, M.col,
+                                                                                M.val.astype(np.float64))
+        orc = oracle.OracleRun(M64, kw["A_p"], kw["C_p"], kw["dt"], R, kw["pairs"], seed=kw["seed"],
+                               stream=kw["stream_id"], block_len=50).run(1000)
+        m_o, se_o = orc.estimates()
+        tol = 1e-10 if prec == fth.FTH_FP64 else 1e-4
+        e_est, e_se = normwise(est, m_o), normwise(se, se_o)
+        print(f"  {name}: packed={info['packed']} est {e_est:.2e} stderr {e_se:.2e}", flush=True)
+        assert e_est <= 10 * tol, name
+        assert e_se <= (1e-6 if prec == fth.FTH_FP64 else 1e-2), name
+        assert info["packed"] == (1 if prec == fth.FTH_FP32 else 0), name
+
+
+def test_admission_does_not_wait_for_slow_request():
+    """A long request's work is issued in chunks of about the quantum, so a
+    request that arrives while it runs starts within a few chunks and finishes
+    long before it, instead of waiting for a whole check interval of the slow
+    request."""
+    slow = dict(band_request(200_000, 71, 41), precision=fth.FTH_FP64)
+    srv = fth.Server(steps_per_tick=2000, quantum_ms=10)
+    a = srv.submit(**slow, replicas=32, block_len=100, max_steps=4000, target=0.0)
+    for _ in range(3):
+        srv.tick()
+    b = srv.submit(**lap_request(8, 72, 42), block_len=20, max_steps=200, target=0.0)
+    run_to_done(srv, [a, b])
+    pa, pb = srv.poll(a), srv.poll(b)
+    wait = pb["t_start"] - pb["t_submit"]
+    print(f"[serve] slow request {pa['t_finish'] - pa['t_start']:.3f} s in {pa['chunks']} chunks; "
+          f"arrival waited {wait * 1e3:.1f} ms, finished after {pb['t_finish'] - pb['t_submit']:.3f} s", flush=True)
+    assert pa["chunks"] > 2 * 4000 // 2000   # cut below the check interval
+    assert pb["t_finish"] < pa["t_finish"]
+    assert wait < 0.25 * (pa["t_finish"] - pa["t_start"])
+
+
+def test_dense_and_packed_chunks_overlap():
+    """A dense GEMM request and a packed sparse request run on their own
+    streams: on the device clock (HIP events around every chunk), the two
+    requests' chunk time adds up to more than the span they occupied
+    together, so their kernels ran at the same time."""
+    d = dense_request(8192, 81, 51)
+    srv = fth.Server(steps_per_tick=200, quantum_ms=-1)
+    ids = [srv.submit(**d, replicas=128, block_len=100, max_steps=1000, target=0.0),
+           srv.submit(**band_request(100_000, 82, 52), block_len=100, max_steps=1000, target=0.0)]
+    run_to_done(srv, ids)
+    dn, sp = (srv.poll(i) for i in ids)
+    assert dn["packed"] == 0 and sp["packed"] == 1
+    span = max(dn["device_last_ms"], sp["device_last_ms"]) - min(dn["device_first_ms"], sp["device_first_ms"])
+    busy = dn["device_ms"] + sp["device_ms"]
+    print(f"[serve] dense {dn['device_ms']:.1f} ms in {dn['chunks']} chunks, sparse {sp['device_ms']:.1f} ms "
+          f"in {sp['chunks']} chunks, together {span:.1f} ms on the device clock", flush=True)
+    assert busy > 1.25 * span
+
+
+def test_spectral_map_and_unscale_in_serving():
+    """A request with a spectral map (Sec. I) is run on M' = r M with the GLE
+    scaled by (alpha, gamma) and its x^-1/2 estimates are mapped back: equal
+    to a standalone context with the same options, unscaled by fth_unscale."""
+    x = lap_request(10, 91, 61)
+    g = fi.load_gle("invsqrt_ns4")
+    lo, hi = g.meta["window_lambda"]
+    r = hi / (fi.laplacian3d_lambda_max(10, 0.1) * 1.5)
+    opts = dict(scale_r=r, gle_alpha=1.3, gle_gamma=0.8)
+    srv = fth.Server(steps_per_tick=100)
+    rid = srv.submit(**x, block_len=50, max_steps=500, target=0.0, unscale_target=fth.FTH_TARGET_INVSQRT, **opts)
+    run_to_done(srv, [rid])
+    est, se = srv.result(rid)
+    sol = fth.Solver(x["M"], x["A_p"], x["C_p"], x["dt"], pairs=x["pairs"], replicas=32, seed=x["seed"],
+                     stream_id=x["stream_id"], block_len=50, **opts).run(500)
+    e0, s0, _ = sol.read()
+    w = (x["pairs"][:, 0] == x["pairs"][:, 1]).astype(np.float64)
+    e1, s1 = fth.fth_unscale(fth.FTH_TARGET_INVSQRT, r, 0.0, 1.3, 0.8, w, e0, s0)
+    assert np.array_equal(est, e1) and np.array_equal(se, s1)
+
+
+def test_failed_admission_does_not_stop_the_others():
+    bad = dense_request(700, 101, 71)   # R = 48 is not a dense matrix-core width
+    good = lap_request(8, 102, 72)
+    srv = fth.Server(steps_per_tick=50)
+    ib = srv.submit(**bad, replicas=48, max_steps=100, target=0.0)
+    ig = srv.submit(**good, block_len=10, max_steps=100, target=0.0)
+    run_to_done(srv, [ib, ig])
+    assert srv.poll(ib)["state"] == fth.FTH_REQ_FAILED and srv.poll(ib)["status"] == fth.FTH_EUNSUPPORTED
+    assert srv.poll(ig)["state"] == fth.FTH_REQ_DONE and srv.poll(ig)["steps"] == 100
