@@ -236,6 +236,26 @@ fth_status fth_set_state(fth_ctx* ctx, const double* q, const double* p, const d
  * FTH_ESTATE before R is fixed; FTH_EUNSUPPORTED for CSR contexts. */
 fth_status fth_force(fth_ctx* ctx, const double* q, double* F);
 
+/* For callers that cannot allocate device memory (code under HIP graph
+ * capture, tight serving loops, harnesses that forbid hipMalloc): the dense
+ * force of fth_force, F = -M q, with q and F as DEVICE arrays in the state
+ * precision (float for FTH_FP32_BF16X3, double for FTH_FP64; q[n*R] and
+ * F[n*R], index i*R + r, caller-owned) and the work buffers (the padded or
+ * bf16-split copy of q and the split-K partial sums) in a fixed library
+ * array of 64 MiB per GPU instead of per-call allocations.  The result is
+ * bit-identical to fth_force's.  Nothing is allocated or freed: the call
+ * enqueues four kernels on hip_stream (NULL: the context's stream) and
+ * returns; F is ready when that stream reaches them.  Every call on one GPU
+ * uses the same array, so calls that overlap on one GPU (other streams,
+ * other threads) race; a call's work space keeps its contents afterwards.
+ * The first call on a device looks the array up (no allocation).
+ * Errors: FTH_EINVAL (NULL pointers, or a system whose work space exceeds
+ * the 64 MiB array: 4 (1 + ksplit) P R bytes in the split form, 8 (1 +
+ * ksplit) P R in FP64, P = n rounded up to the padded size), FTH_ESTATE
+ * before R is fixed, FTH_EUNSUPPORTED for CSR or one-workgroup dense
+ * contexts, FTH_EDEVICE on a launch failure. */
+fth_status fth_force_noalloc(fth_ctx* ctx, const void* q, void* F, void* hip_stream);
+
 /* GPU time in milliseconds of the most recent fth_run, measured with HIP
  * events on the context's stream around its launches (0 before any run). */
 double fth_last_run_ms(const fth_ctx* ctx);

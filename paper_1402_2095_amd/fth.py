@@ -30,7 +30,7 @@ EXPORTS = [
     "fth_server_create", "fth_server_submit", "fth_server_tick", "fth_server_poll", "fth_server_result",
     "fth_server_cancel", "fth_server_clock", "fth_server_stats", "fth_server_destroy",
     "fth_spectral_map", "fth_gershgorin", "fth_unscale", "fth_device_bytes", "fth_save", "fth_load",
-    "fth_set_steps_per_graph",
+    "fth_force_noalloc", "fth_set_steps_per_graph",
 ]
 FTH_TARGET_INVSQRT, FTH_TARGET_LN, FTH_TARGET_EXPNEG = 0, 1, 2
 FTH_REQ_QUEUED, FTH_REQ_RUNNING, FTH_REQ_DONE, FTH_REQ_FAILED, FTH_REQ_CANCELLED = 0, 1, 2, 3, 4
@@ -144,6 +144,7 @@ def lib():
             "fth_version": (ctypes.c_char_p, []),
             "fth_noise_sample": (i32, [u64, ctypes.c_uint32, i64, P, P, P, P, i32, P, P]),
             "fth_force": (i32, [P, P, P]),
+            "fth_force_noalloc": (i32, [P, P, P, P]),
             "fth_set_steps_per_graph": (i32, [P, i32]),
             "fth_server_create": (i32, [P, P]),
             "fth_server_submit": (i32, [P, P, P]),
@@ -293,6 +294,13 @@ def fth_force(ctx, q):
     F = np.zeros_like(q)
     _check(lib().fth_force(ctx, _p(q), _p(F)))
     return F
+
+
+def fth_force_noalloc(ctx, q_ptr: int, F_ptr: int, stream_ptr=None):
+    """F = -M q on device arrays (raw device addresses in the state
+    precision); enqueued on the stream, nothing allocated."""
+    _check(lib().fth_force_noalloc(ctx, ctypes.c_void_p(q_ptr), ctypes.c_void_p(F_ptr),
+                                   ctypes.c_void_p(stream_ptr) if stream_ptr else None))
 
 
 def fth_last_run_ms(ctx) -> float:
