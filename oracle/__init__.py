@@ -31,22 +31,28 @@ _LIB = os.path.join(_HERE, "liboracle.so")
 _lib = None
 
 
-def build(force: bool = True) -> str:
-    """Compile the C step loop with gcc (FP64, -O2, OpenMP)."""
-    if force or not os.path.exists(_LIB):
-        tmp = _LIB + ".tmp"
+def build(force: bool = True, sanitize: bool = False, out: str | None = None) -> str:
+    """Compile the C step loop with gcc (FP64, -O2, OpenMP); with sanitize,
+    a copy instrumented with AddressSanitizer and UndefinedBehaviorSanitizer
+    (to be loaded with gcc's libasan preloaded)."""
+    path = out or _LIB
+    if force or not os.path.exists(path):
+        tmp = path + ".tmp"
+        flags = ["-g", "-fsanitize=address,undefined", "-fno-sanitize-recover=undefined",
+                 "-fno-omit-frame-pointer"] if sanitize else []
         subprocess.check_call(["gcc", "-O2", "-fopenmp", "-fPIC", "-shared", "-std=c11",
-                               "-ffp-contract=off", _SRC, "-o", tmp, "-lm"])
-        os.replace(tmp, _LIB)
-    return _LIB
+                               "-ffp-contract=off", *flags, _SRC, "-o", tmp, "-lm"])
+        os.replace(tmp, path)
+    return path
 
 
 def lib():
     global _lib
     if _lib is None:
-        if not os.path.exists(_LIB):
+        path = os.environ.get("FTH_ORACLE_LIB", _LIB)   # another build of the same source (sanitizer runs)
+        if path == _LIB and not os.path.exists(_LIB):
             build(force=True)
-        L = ctypes.CDLL(_LIB)
+        L = ctypes.CDLL(path)
         P = ctypes.c_void_p
         i64, u64, u32 = ctypes.c_int64, ctypes.c_uint64, ctypes.c_uint32
         L.orc_philox4x32_10.argtypes = [P, P, P]

@@ -79,6 +79,49 @@ def build(verbose: bool = True, jobs: int | None = None, incremental: bool = Fal
     return LIB
 
 
+# Host translation units (no kernels): the part a CPU sanitizer build covers.
+HOST_SOURCES = ["fth_api.cpp", "fth_linalg.cpp", "fth_scale.cpp", "fth_server.cpp", "noalloc.hip"]
+SANITIZE = ["-Xarch_host", "-fsanitize=address", "-Xarch_host", "-fsanitize=undefined",
+            "-Xarch_host", "-fno-sanitize-recover=undefined", "-Xarch_host", "-fno-omit-frame-pointer"]
+
+
+def build_sanitized(out: str) -> str:
+    """A copy of the library whose host code is built with AddressSanitizer
+    and UndefinedBehaviorSanitizer (device code as in the normal build; the
+    sanitizers apply to the host side only).  Load it with the compiler's
+    shared ASan runtime preloaded."""
+    os.makedirs(BUILD, exist_ok=True)
+    objs = []
+    for src in sources():
+        base = os.path.basename(src)
+        if base in HOST_SOURCES:
+            obj = os.path.join(os.path.dirname(out), base + ".san.o")
+            cmd = [hipcc(), *COMMON, "-g", "-x", "hip", *DEVICE, *SANITIZE, "-I", CSRC, "-c", src, "-o", obj]
+            res = subprocess.run(cmd, capture_output=True, text=True)
+            if res.returncode != 0:
+                raise RuntimeError(f"compile failed: {' '.join(cmd)}\n{res.stdout}\n{res.stderr}")
+            objs.append(obj)
+        else:
+            objs.append(_compile(src, incremental=True))
+    cmd = [hipcc(), f"--offload-arch={ARCH}", "-shared", "-fPIC", *SANITIZE, "-Xarch_host", "-shared-libasan",
+           *objs, "-o", out]
+    res = subprocess.run(cmd, capture_output=True, text=True)
+    if res.returncode != 0:
+        raise RuntimeError(f"link failed: {' '.join(cmd)}\n{res.stdout}\n{res.stderr}")
+    return out
+
+
+def asan_runtime() -> str:
+    """The shared ASan runtime of the compiler that builds the library."""
+    res = subprocess.run([hipcc(), "-print-file-name=libclang_rt.asan-x86_64.so"], capture_output=True, text=True)
+    path = res.stdout.strip()
+    if not os.path.isabs(path) or not os.path.exists(path):
+        import glob
+        cands = glob.glob("/opt/rocm/llvm/lib/clang/*/lib/linux/libclang_rt.asan-x86_64.so")
+        path = cands[0] if cands else ""
+    return path
+
+
 if __name__ == "__main__":
     build(incremental="--incremental" in sys.argv)
     sys.exit(0)

@@ -13,7 +13,8 @@ import os
 import numpy as np
 
 _PKG = os.path.dirname(os.path.abspath(__file__))
-LIB_PATH = os.path.join(_PKG, "libfth.so")
+# FTH_LIB_PATH selects another build of the library (e.g. the host-sanitizer build)
+LIB_PATH = os.environ.get("FTH_LIB_PATH", os.path.join(_PKG, "libfth.so"))
 
 FTH_OK, FTH_EINVAL, FTH_ENOMEM, FTH_EDEVICE, FTH_ESTATE, FTH_ENONFINITE, FTH_EUNSUPPORTED = 0, -1, -2, -3, -4, -5, -6
 FTH_DENSE, FTH_CSR = 0, 1
