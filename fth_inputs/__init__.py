@@ -132,6 +132,31 @@ def laplacian3d_lambda_max(n: int, sigma: float) -> float:
     return sigma + 3.0 * float(mx)
 
 
+def insulator3d_csr(n: int, delta: float = 1.2, hop: float = 0.9797958971132712, shift: float = 6.1,
+                    dtype=np.float32) -> CSR:
+    """A gapped stand-in for a tight-binding insulator (the setting of the
+    Fermi-function example, Sec. II): an n^3 periodic cubic lattice (n even),
+    on-site shift + delta on sites with x + y + z even and shift - delta on
+    the others, hopping -hop to the six nearest neighbours.  Its spectrum is
+    shift -/+ sqrt(delta^2 + hop^2 gamma_k^2), gamma_k = sum_d 2 cos(2 pi k_d / n):
+    a lower and an upper band of N/2 states each, separated by a gap of
+    2 delta around shift (exactly, when 4 divides n).  The defaults give
+    [0.1, 4.9] and [7.3, 12.1]."""
+    if n % 2:
+        raise ValueError("the two sublattices need an even n")
+    N = n ** 3
+    idx = np.arange(N, dtype=np.int64)
+    x, rem = np.divmod(idx, n * n)
+    y, z = np.divmod(rem, n)
+    par = (x + y + z) % 2
+    rows, cols, vals = [idx], [idx], [np.where(par == 0, shift + delta, shift - delta)]
+    for dx, dy, dz in ((1, 0, 0), (-1, 0, 0), (0, 1, 0), (0, -1, 0), (0, 0, 1), (0, 0, -1)):
+        rows.append(idx)
+        cols.append(lattice_index((x + dx) % n, (y + dy) % n, (z + dz) % n, n))
+        vals.append(np.full(N, -hop))
+    return _coo_to_csr(N, np.concatenate(rows), np.concatenate(cols), np.concatenate(vals), dtype)
+
+
 # --------------------------------------------------------------------------
 # Random banded SPD (7 nonzeros per row)
 # --------------------------------------------------------------------------

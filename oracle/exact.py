@@ -178,6 +178,45 @@ def laplacian_eigs(n: int, sigma: float) -> np.ndarray:
     return sigma + c[:, None, None] + c[None, :, None] + c[None, None, :]
 
 
+def insulator_eigs(n: int, delta: float, hop: float, shift: float) -> np.ndarray:
+    """Spectrum of the two-sublattice cubic lattice (on-site shift +/- delta
+    by the parity of x + y + z, nearest-neighbour hopping -hop, periodic, n
+    even), all N = n^3 values.  The staggered potential couples the Bloch
+    waves k and k + (pi, pi, pi), whose hopping energies are -hop gamma_k and
+    +hop gamma_k; each such pair is a 2 x 2 block [[-hop g, delta], [delta,
+    hop g]] with eigenvalues +/- sqrt(delta^2 + hop^2 g^2).  Summed over the
+    whole grid every pair is met twice, so the spectrum is shift +/- E_k over
+    the grid, each sign taken once per pair: the multiset {shift - E_k} over
+    half the grid and {shift + E_k} over the other half, which for sums is
+    half of each over the whole grid."""
+    c = 2.0 * np.cos(2.0 * np.pi * np.arange(n) / n)
+    gam = (c[:, None, None] + c[None, :, None] + c[None, None, :]).ravel()
+    E = np.sqrt(delta * delta + hop * hop * gam * gam)
+    # k and k + Q give the same E: keep the half of the grid with k_x < n/2 (one of each pair)
+    kx = np.repeat(np.arange(n), n * n)
+    Eh = E[kx < n // 2]
+    return np.sort(np.concatenate([shift - Eh, shift + Eh]))
+
+
+def insulator_sublattice_diagonal(n: int, delta: float, hop: float, shift: float, g_of_lam):
+    """Diagonal of g(M) for the two-sublattice lattice, which takes one value
+    on each sublattice (translation invariance within it): (even, odd) for
+    sites with x + y + z even (on-site shift + delta) and odd.  In the basis
+    of the two sublattice Bloch sums at k (one k per pair k, k + Q), M is
+    [[shift + delta, -hop g], [-hop g, shift - delta]]; its eigenvector of
+    shift + E puts weight (1 + delta / E) / 2 on the even sublattice and that
+    of shift - E weight (1 - delta / E) / 2, so the even diagonal is the
+    average over the N/2 values of k of those weights times g."""
+    c = 2.0 * np.cos(2.0 * np.pi * np.arange(n) / n)
+    gam = (c[:, None, None] + c[None, :, None] + c[None, None, :])[: n // 2].ravel()
+    E = np.sqrt(delta * delta + hop * hop * gam * gam)
+    gp, gm = g_of_lam(shift + E), g_of_lam(shift - E)
+    w = delta / E
+    even = np.mean(0.5 * (1 + w) * gp + 0.5 * (1 - w) * gm)
+    odd = np.mean(0.5 * (1 - w) * gp + 0.5 * (1 + w) * gm)
+    return float(even), float(odd)
+
+
 def laplacian_function(n: int, sigma: float, g_of_lam) -> np.ndarray:
     """g(M) for the periodic n^3 Laplacian + sigma, as the translation
     invariant kernel C(dx, dy, dz) = ifftn(g(lambda(k))) (the DFT diagonalises

@@ -106,6 +106,45 @@ def test_m1_log_det_via_ln_target_and_trace():
     assert abs(ref_h - exact_ld) <= bound
 
 
+def test_m1_log_det_via_momentum_form():
+    """log det M1 the way the paper estimates it (Eq. 7 and the Sec. II
+    examples): a GLE fitted so that <p^2>(omega) = ln omega^2 over
+    omega in [e, 100 e], eight extra momenta, no rescaling needed since M1's
+    spectrum [85, 180] sits inside the window.  log det M = Tr ln M is the
+    kinetic trace sum_i <p_i^2>.  Statistical parity against the exact
+    momentum response of the integrated step, sum_k gh_p(lambda_k); the model
+    error (fit + step) against slogdet stays within the fit report."""
+    g = fi.load_gle("ln_p_ns8")
+    assert g.meta["form"] == "p"
+    lo_w, hi_w = g.meta["window_lambda"]
+    M = fi.m1_lattice_csr(6, 3)
+    n = M.n
+    lam = np.linalg.eigvalsh(csr_to_dense(M))
+    assert lo_w <= lam.min() and lam.max() <= hi_w
+    _, hi = fth.fth_gershgorin(M)
+    h = 0.1 / np.sqrt(hi)
+    sol = fth.Solver(M, g.A_p, g.C_p, h, replicas=128, precision=fth.FTH_FP32, seed=31, burn_in=5000,
+                     block_len=5000, acc_diag=True, acc_pp=True, acc_trace=True)
+    sol.run(100000)
+    est, se, _ = sol.read()
+    assert est.shape == (2 * n + 3,)       # q diagonal, p diagonal, Tr q^2, q^T M q, Tr p^2
+    logdet, se_ld = est[-1], se[-1]
+    T, S = oracle.propagator(g.A_p, g.C_p, h)
+    ref_h = float(np.sum(exact.gh_p(lam, g.A_p, g.C_p, h, T, S)))
+    exact_ld = float(np.sum(np.log(lam)))
+    assert exact_ld == pytest.approx(float(np.linalg.slogdet(csr_to_dense(M))[1]), rel=1e-12)
+    z = (logdet - ref_h) / se_ld
+    print(f"[M1 logdet p-form] est {logdet:.3f} +- {se_ld:.3f}, exact response {ref_h:.3f}, "
+          f"slogdet {exact_ld:.3f}, z {z:.2f}", flush=True)
+    assert abs(z) < 5.0
+    # the per-row diagonal <p_i^2> sums to the trace output
+    assert np.sum(est[n:2 * n]) == pytest.approx(logdet, rel=1e-5)
+    rep = g.meta["fit_report"]
+    bound = (rep["max_rel_err"] + 2 * rep["max_rel_dt_err_gh_vs_g0"]) * np.sum(np.abs(np.log(lam)))
+    assert abs(ref_h - exact_ld) <= bound
+    assert abs(logdet - exact_ld) <= bound + 5 * se_ld
+
+
 def test_m2_trace_of_exponential():
     """The paper's M2 (dense, eigenvalues in (-300, 300) by Gerschgorin):
     Tr exp(-M2 / 100) from the exp(-x) GLE on M' = M2 / 100 + 3.1 I, undone by

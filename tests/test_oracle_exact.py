@@ -174,3 +174,45 @@ def test_tau_slowest_from_discrete_step_map(name):
             errs.append(abs(-h / np.log(rho) / want - 1.0))
         assert errs[1] < 2e-3, (lam, errs)
         assert errs[1] < 0.75 * errs[0] + 1e-9  # shrinks with h
+
+
+@pytest.mark.parametrize("n", [4, 6, 8])
+def test_insulator_closed_form_spectrum(n):
+    """The two-sublattice lattice's closed-form spectrum against a dense
+    eigensolver: half the states below the gap, none inside (4.9, 7.3) with
+    the default parameters, bands exactly [0.1, 4.9] and [7.3, 12.1]."""
+    M = fth_inputs.insulator3d_csr(n, dtype=np.float64)
+    A = np.zeros((M.n, M.n))
+    for i in range(M.n):
+        for k in range(M.row_ptr[i], M.row_ptr[i + 1]):
+            A[i, M.col[k]] += M.val[k]
+    assert np.array_equal(A, A.T)
+    ev = np.linalg.eigvalsh(A)
+    cf = exact.insulator_eigs(n, 1.2, 0.9797958971132712, 6.1)
+    assert np.allclose(ev, cf, rtol=0, atol=1e-12)
+    assert np.sum(ev < 6.1) == M.n // 2
+    assert np.max(ev[ev < 6.1]) <= 4.9 + 1e-12 and np.min(ev[ev > 6.1]) >= 7.3 - 1e-12
+    assert ev.min() == pytest.approx(0.1, abs=1e-12) and ev.max() == pytest.approx(12.1, abs=1e-12)
+
+
+def test_insulator_sublattice_diagonal_against_eigh():
+    """Sublattice-resolved diagonal of g(M) from the 2 x 2 Bloch blocks
+    against U g(Lambda) U^T from a dense eigensolver, for g = exp(-x / 4) and
+    g = 1 / x; every site of a sublattice takes the same value."""
+    n = 6
+    M = fth_inputs.insulator3d_csr(n, dtype=np.float64)
+    A = np.zeros((M.n, M.n))
+    for i in range(M.n):
+        for k in range(M.row_ptr[i], M.row_ptr[i + 1]):
+            A[i, M.col[k]] += M.val[k]
+    lam, U = np.linalg.eigh(A)
+    idx = np.arange(M.n)
+    x, rem = np.divmod(idx, n * n)
+    y, z = np.divmod(rem, n)
+    even = (x + y + z) % 2 == 0
+    for fn in (lambda v: np.exp(-v / 4), lambda v: 1.0 / v):
+        d = np.einsum("ik,k,ik->i", U, fn(lam), U)
+        e, o = exact.insulator_sublattice_diagonal(n, 1.2, 0.9797958971132712, 6.1, fn)
+        assert np.allclose(d[even], e, rtol=1e-12, atol=1e-14)
+        assert np.allclose(d[~even], o, rtol=1e-12, atol=1e-14)
+        assert not np.isclose(e, o)
