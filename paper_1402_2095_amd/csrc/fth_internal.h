@@ -122,10 +122,12 @@ struct DenseGemmArgs {
 // Largest workgroup of the temporally blocked step: a row's (p, s) and CSR
 // entries stay in registers for the whole launch, so larger NS (and FP64)
 // need the register file of fewer threads.
-// Momentum-form and trace accumulators (xtra) need a few more registers.
+// Momentum-form and trace accumulators (xtra) need a few more registers:
+// with them, 1024 threads only for FP32 at ns <= 4 (a few more spilled
+// registers, reloaded once per tile).
 constexpr int tb_max_block(bool f64, int ns, bool xtra = false) {
     const int b = f64 ? (ns == 0 ? 1024 : ns <= 4 ? 512 : 256) : (ns <= 4 ? 1024 : ns <= 9 ? 512 : 256);
-    return xtra && b > 512 ? 512 : b;
+    return xtra && b > 512 && (f64 || ns > 4) ? 512 : b;
 }
 
 // Extra arguments of the temporally blocked sparse step.
@@ -158,15 +160,15 @@ struct TbSlotRow {
 static_assert(sizeof(TbSlotRow<float>) % 16 == 0 && sizeof(TbSlotRow<double>) % 16 == 0, "slot rows are 16-byte chunks");
 
 // Bookkeeping words a wave stages per tile with 4-byte direct-to-LDS loads
-// (256 bytes each): the diagonal block sum (two words), the pair snapshot
-// slot and, with momentum-form accumulators, their block sum (two words).
-constexpr int tbp_aux_words(bool xtra) { return xtra ? 5 : 3; }
+// (256 bytes each): the diagonal block sum (two words) and the pair snapshot
+// slot.  (The momentum-form block sum is prefetched into a register.)
+constexpr int kTbpAuxWords = 3;
 
 // LDS bytes of the persistent blocked step for a workgroup of `block`
 // threads (4 replicas per thread): q of the extended rows twice, the trace
 // row sums (if kept) and each wave's staging area (state, slot rows and
 // bookkeeping of the next tile).
-constexpr size_t tbp_lds_bytes(bool f64, int ns, int block, int R, int T, bool traces, bool xtra) {
+constexpr size_t tbp_lds_bytes(bool f64, int ns, int block, int R, int T, bool traces) {
     const size_t rb = f64 ? 8 : 4;
     const size_t E = size_t(block) * 4 / size_t(R);
     const size_t q = 2 * E * size_t(R) * rb;
@@ -175,7 +177,7 @@ constexpr size_t tbp_lds_bytes(bool f64, int ns, int block, int R, int T, bool t
     const size_t rows_per_wave = 64 / (size_t(R) / 4);
     const size_t sb = f64 ? sizeof(TbSlotRow<double>) : sizeof(TbSlotRow<float>);
     const size_t ci = (rows_per_wave * sb + 1023) / 1024;  // slot-row loads per wave
-    const size_t stage = (size_t(block) / 64) * ((size_t(ns + 2) * vi + ci) * 1024 + size_t(tbp_aux_words(xtra)) * 256);
+    const size_t stage = (size_t(block) / 64) * ((size_t(ns + 2) * vi + ci) * 1024 + size_t(kTbpAuxWords) * 256);
     return q + tr + stage;
 }
 

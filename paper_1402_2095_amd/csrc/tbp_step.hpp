@@ -88,7 +88,7 @@ __global__ __launch_bounds__(tb_max_block(sizeof(Real) == 8, NS, XTRA)) void tbp
     const int wave = __builtin_amdgcn_readfirstlane(int(threadIdx.x) >> 6);  // uniform in the wave: scalar
     const int rows_per_wave = 64 >> lg;
     const int CI = (rows_per_wave * SB + 1023) / 1024;
-    constexpr int AUX = tbp_aux_words(XTRA);
+    constexpr int AUX = kTbpAuxWords;
 
     Real* qlds = reinterpret_cast<Real*>(tb_smem);  // [2][E][R]
     double* trl = reinterpret_cast<double*>(qlds + int64_t(2) * E * R);
@@ -141,16 +141,21 @@ __global__ __launch_bounds__(tb_max_block(sizeof(Real) == 8, NS, XTRA)) void tbp
             stage4(reinterpret_cast<const char*>(a.dblk + i) + 4, waux + 256);
         }
         if (tb.pair_slot != nullptr) stage4(tb.pair_slot + i, waux + 512);
-        if (XTRA && a.dp_blk != nullptr) {
-            stage4(reinterpret_cast<const char*>(a.dp_blk + i), waux + 768);
-            stage4(reinterpret_cast<const char*>(a.dp_blk + i) + 4, waux + 1024);
-        }
+    };
+    // The momentum-form block sum of a row is prefetched into a register
+    // instead (LDS holds no room for it at 1024 threads); the tile-start wait
+    // for the staged loads covers it too.  Only output rows use it, and a row
+    // is an output row of one tile only, so no other tile writes it meanwhile.
+    auto fetch_blkp = [&](int64_t t, int e) -> double {
+        if (!(XTRA && a.dp_blk != nullptr)) return 0.0;
+        return a.dp_blk[min(max(t * T - H + e, int64_t(0)), Nm1)];
     };
 
     const Real* T_ = a.TS;
     const Real* S_ = a.TS + D * D;
     bool ok = true;
     issue(t_begin, e, r0, lane);
+    double blkp_next = fetch_blkp(t_begin, e);
 #pragma unroll 1
     for (int64_t t = t_begin; t < t_end; ++t) {
         // Per-tile copies of the thread's coordinates that the compiler must
@@ -167,7 +172,7 @@ __global__ __launch_bounds__(tb_max_block(sizeof(Real) == 8, NS, XTRA)) void tbp
         int32_t pslot = -1;
         if (output && rq == 0) {
             if (a.dblk != nullptr) blk = stage_f64(waux, 0, lane_t);
-            if (XTRA && a.dp_blk != nullptr) blkp = stage_f64(waux, 3, lane_t);
+            if (XTRA && a.dp_blk != nullptr) blkp = blkp_next;
         }
         if (output && tb.pair_slot != nullptr) pslot = *reinterpret_cast<const int32_t*>(waux + 512 + lane_t * 4);
         RowState<Real, NS, RPT> st;
@@ -183,7 +188,10 @@ __global__ __launch_bounds__(tb_max_block(sizeof(Real) == 8, NS, XTRA)) void tbp
         const uint64_t offs = *reinterpret_cast<const uint64_t*>(srow->off);
         const int nz = srow->nz;
         __builtin_amdgcn_s_waitcnt(kWaitLgkm0);  // staging read into registers before it is refilled
-        if (t + 1 < t_end) issue(t + 1, e_t, r0_t, lane_t);
+        if (t + 1 < t_end) {
+            issue(t + 1, e_t, r0_t, lane_t);
+            blkp_next = fetch_blkp(t + 1, e_t);
+        }
         store_vec<Real, RPT>(qlds + int64_t(e_t) * R + r0_t, st.q);
         __syncthreads();
 
@@ -332,7 +340,7 @@ int launch_tbp_step_impl(const StepArgs<Real>& a, const TbArgs<Real>& tb, const 
     if (fn == nullptr) return -2;
     const int block = tb.E << a.lg_tpr;
     if (block > tb_max_block(sizeof(Real) == 8, L.ns, x) || block % 64 != 0) return -3;
-    const size_t lds = tbp_lds_bytes(sizeof(Real) == 8, L.ns, block, a.R, tb.T, a.tpart != nullptr, x);
+    const size_t lds = tbp_lds_bytes(sizeof(Real) == 8, L.ns, block, a.R, tb.T, a.tpart != nullptr);
     StepArgs<Real> aa = a;
     TbArgs<Real> tt = tb;
     int kk = k;

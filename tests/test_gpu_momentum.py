@@ -96,20 +96,38 @@ def test_blocked_momentum_and_traces_parity(kt):
                fi.random_pairs(M.n, 40, 18), f"blocked KT={kt}", f"KT={kt}", temporal_steps=kt)
 
 
-@pytest.mark.parametrize("kt", [3, 5])
-def test_blocked_momentum_bit_identical(kt):
+@pytest.mark.parametrize("kt,threads", [(3, 512), (3, 1024), (5, 1024)])
+@pytest.mark.parametrize("persistent", [0, -1], ids=["persistent", "per-tile"])
+@pytest.mark.parametrize("traces", [False, True], ids=["pp", "pp+traces"])
+def test_blocked_momentum_bit_identical(kt, threads, persistent, traces):
+    """Momentum-form (and trace) accumulators in both blocked forms, up to
+    1024 threads per workgroup in FP32, reproduce the one-step kernel bit for
+    bit: state and the q-q and p-p accumulators; the trace sums up to the
+    order of their FP64 additions."""
     M = fi.banded_spd_csr(20011, 17)
     h = fi.dt_rule(fi.gershgorin_max(M))
     g = fi.load_gle("fermi_b20_ns4")
-    kw = dict(pairs=fi.random_pairs(M.n, 64, 15), replicas=32, seed=8, acc_diag=True, acc_pp=True, burn_in=2,
-              block_len=4, steps_per_graph=10)
-    a = fth.Solver(M, g.A_p, g.C_p, h, temporal_steps=kt, **kw).run(1).run(44)
+    kw = dict(pairs=fi.random_pairs(M.n, 64, 15), replicas=32, seed=8, acc_diag=True, acc_pp=True,
+              acc_trace=traces, burn_in=2, block_len=4, steps_per_graph=10)
+    a = fth.Solver(M, g.A_p, g.C_p, h, temporal_steps=kt, temporal_threads=threads, temporal_persistent=persistent,
+                   **kw).run(1).run(44)
     b = fth.Solver(M, g.A_p, g.C_p, h, temporal_steps=-1, **kw).run(1).run(44)
-    assert "tb_step_kernel" in a.kernel_name or "tbp_step_kernel" in a.kernel_name
+    print(f"[tb pp] {a.kernel_name}", flush=True)
+    assert f"KT={kt}> block={threads}" in a.kernel_name
+    if persistent == 0 and not traces:   # the persistent form's staging fits at every shape here
+        assert "tbp_step_kernel" in a.kernel_name
     for x, y in zip(a.state(), b.state()):
         assert np.array_equal(x, y)
+    # the trace sums (the last three outputs) are folded per row tile, and the two
+    # kernels tile rows differently: equal up to the order of FP64 additions
+    nt = 3 if traces else 0
     for x, y in zip(a.accumulators()[:3], b.accumulators()[:3]):
-        assert np.array_equal(x, y)
+        assert np.array_equal(x[:len(x) - nt], y[:len(y) - nt])
+        if traces:
+            assert np.allclose(x[-3:], y[-3:], rtol=1e-12, atol=0)
+    ea, sa, _ = a.read()
+    eb, sb, _ = b.read()
+    assert np.array_equal(ea[:len(ea) - nt], eb[:len(eb) - nt]) and np.array_equal(sa[:len(sa) - nt], sb[:len(sb) - nt])
 
 
 def test_momentum_estimates_match_exact_response():
