@@ -1,5 +1,6 @@
-"""Offline GLE fitter: (A_p, C_p) whose stationary <q^2>(omega) follows a
-target f(omega^2) over a spectral window.
+"""Offline GLE fitter: (A_p, C_p) whose stationary <q^2>(omega) (position
+form) or <p^2>(omega) (momentum form, Eq. 7) follows a target f(omega^2) over
+a spectral window.
 
 TEST INFRASTRUCTURE / INPUT PREPARATION (part of the oracle).  It writes the
 parameter files under ``fth_inputs/gle/``; both the oracle and the HIP library
@@ -17,13 +18,16 @@ Lyapunov relation A_p C_p + C_p A_p^T = B_p B_p^T (Sec. I), which keeps C_p
 positive definite and B_p B_p^T positive semi-definite by construction.
 
 Objective (the three requirements of Sec. II):
-  (1) agreement of g0(lambda) = <q^2>(sqrt(lambda)) (or, for a fit at a given
-      time step h, of the exact response g_h of the integrated step, which
-      corrects the time-step error exactly: Sec. II, error paragraph) with f(lambda) on a
-      log-spaced grid over the window: log residuals, or for targets with an
-      exponentially decaying tail (Fermi) residuals relative to max f where
-      f is not negligible plus a hinge penalty that only asks for
-      g0 < delta * max g0 where f < delta (the paper's threshold delta);
+  (1) agreement of g0(lambda) = <q^2>(sqrt(lambda)) or <p^2>(sqrt(lambda))
+      (or, for a fit at a given time step h, of the exact response g_h of
+      the integrated step, which corrects the time-step error exactly: Sec. II,
+      error paragraph) with f(lambda) on a log-spaced grid over the window:
+      log residuals; for targets with an exponentially decaying tail (Fermi,
+      or exp(-x) with a threshold) residuals relative to max f where f is
+      not negligible plus a hinge penalty that only asks for
+      g0 < delta * max g0 where f < delta (the paper's threshold delta); for
+      a step across a spectral gap (zero-temperature Fermi occupation of an
+      insulator, Sec. II) absolute residuals outside the gap, none inside;
   (2) stability for the time step: a_pp, the omega -> infinity limit of the
       friction kernel, kept below omega_max;
   (3) statistical efficiency: a mild penalty on the slowest relaxation time
