@@ -87,17 +87,18 @@ def workload(name: str) -> dict:
                  prec=fth.FTH_FP64 if name.endswith("fp64") else fth.FTH_FP32_BF16X3, steps=2000)
     elif name == "m1-logdet":
         # the paper's M1 (logarithm example): periodic 24^3 lattice, on-site 100, hopping U[0, 2]
-        # to the first six neighbour shells (81 entries per row); log det M = Tr ln M from the
-        # position trace with the ln GLE, run on M' = r M (the spectral map of Sec. I)
+        # to the first six neighbour shells (81 entries per row); log det M = Tr ln M as the
+        # kinetic trace sum_i <p_i^2> with the momentum-form ln GLE (Eq. 7; omega in [e, 100 e],
+        # which holds M1's spectrum without a map)
         M = fi.m1_lattice_csr(24, 6006, dtype=np.float32)
-        g = fi.load_gle("ln_ns4")
-        lo_w, hi_w = g.meta["window_lambda"]
+        g = fi.load_gle("ln_p_ns8")
         _, hi = fth.fth_gershgorin(M)
-        w.update(desc={"workload": "M1 lattice 24^3 (N=13824, 81 nonzeros/row, CSR), log det via Tr ln",
-                       "gle": "ns=4, ln target, M' = r M", "replicas": 32,
-                       "estimates": "diagonal + 1024 pairs + traces", "steps_in_config": 20000},
-                 M=M, g=g, h=0.1 / np.sqrt(hi_w), R=32, pairs=fi.random_pairs(M.n, 1024, 6007), prec=fth.FTH_FP32,
-                 steps=20000, extra=dict(scale_r=hi_w / hi, acc_trace=True))
+        w.update(desc={"workload": "M1 lattice 24^3 (N=13824, 81 nonzeros/row, CSR), log det via the kinetic trace",
+                       "gle": "ns=8, ln target, momentum form (Eq. 7)", "replicas": 32,
+                       "estimates": "diagonal + 1024 pairs, position and momentum forms, traces",
+                       "steps_in_config": 20000},
+                 M=M, g=g, h=0.1 / np.sqrt(hi), R=32, pairs=fi.random_pairs(M.n, 1024, 6007), prec=fth.FTH_FP32,
+                 steps=20000, extra=dict(acc_pp=True, acc_trace=True))
     elif name == "m2-exp":
         # the paper's M2 (exponential example): dense, eigenvalues in (-300, 300) by Gerschgorin;
         # Tr exp(-M / 100) with the exp(-x) GLE on M' = M / 100 + 3.1 I
@@ -124,8 +125,9 @@ def step_bytes(w: dict) -> float:
     N R, as derived for the scope table): the state q, p, s_1..s_ns read and
     written once; sparse: the CSR matrix once (32-bit row pointers, 32-bit
     column indices, one value per nonzero) and the FP64 diagonal block
-    accumulator read and written; dense: M once as bf16 hi + lo (4 bytes per
-    entry; FP64: 8).  Selected pairs are negligible and left out."""
+    accumulator (and its momentum-form twin, when kept) read and written;
+    dense: M once as bf16 hi + lo (4 bytes per entry; FP64: 8).  Selected
+    pairs are negligible and left out."""
     from paper_1402_2095_amd import fth
     b = 8 if w["prec"] == fth.FTH_FP64 else 4
     n, R, ns = w["n"], w["R"], w["g"].ns
@@ -133,7 +135,8 @@ def step_bytes(w: dict) -> float:
     if w["dense"]:
         return state + float(n) * n * (8 if w["prec"] == fth.FTH_FP64 else 4)
     M = w["M"]
-    return state + (n + 1) * 4.0 + M.nnz * (4.0 + b) + 16.0 * n
+    acc = 16.0 * n * (2 if w["extra"].get("acc_pp") else 1)   # FP64 block sums: q-q, and p-p when kept
+    return state + (n + 1) * 4.0 + M.nnz * (4.0 + b) + acc
 
 
 def alu_ops_per_row_step(ns: int, nnz_row: float) -> float:
@@ -690,13 +693,15 @@ def main():
         "roofline": roof,
         "cpu_baseline": None,
     }
-    if args.workload in ("m1-logdet", "m2-exp"):  # the trace, mapped back to the original matrix
-        tgt = fth.FTH_TARGET_LN if args.workload == "m1-logdet" else fth.FTH_TARGET_EXPNEG
+    if args.workload == "m1-logdet":   # the kinetic trace (the last output) is Tr ln M itself
+        out["result"] = {"quantity": "log det M", "estimate": float(r["est"][-1]), "stderr": float(r["se"][-1]),
+                         "steps": args.steps + args.warmup}
+    if args.workload == "m2-exp":   # the position trace, mapped back to the original matrix
         k = len(r["est"]) - 2          # position trace (then q^T M q)
-        e_u, s_u = fth.fth_unscale(tgt, w["extra"].get("scale_r", 1.0), w["extra"].get("scale_m", 0.0), 1.0, 1.0,
+        e_u, s_u = fth.fth_unscale(fth.FTH_TARGET_EXPNEG, w["extra"]["scale_r"], w["extra"]["scale_m"], 1.0, 1.0,
                                    [float(w["n"])], r["est"][k:k + 1], r["se"][k:k + 1])
-        out["result"] = {"quantity": "log det M" if tgt == fth.FTH_TARGET_LN else "Tr exp(-M/100)",
-                         "estimate": float(e_u[0]), "stderr": float(s_u[0]), "steps": args.steps + args.warmup}
+        out["result"] = {"quantity": "Tr exp(-M/100)", "estimate": float(e_u[0]), "stderr": float(s_u[0]),
+                         "steps": args.steps + args.warmup}
     if args.workload == "banded1e6" and not args.no_secondary:
         sec = {}
         # warm-ups of about 0.2 s each: the inputs are generated on the host first, and a GPU left
