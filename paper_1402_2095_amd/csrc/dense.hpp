@@ -94,11 +94,10 @@ __device__ __forceinline__ void scatter_chunk(T* __restrict__ dst, const T (&src
 }
 
 // ------------------------------------------------------ split-BF16x3 GEMM
-// A k-step covers 64 consecutive k: one 32 KB tile of M (hi and lo parts),
-// fetched two k-steps ahead, and one 32 KB chunk of q_n, fetched one ahead.
-// M is read once per step, so its loads are non-temporal (they do not evict
-// q_n from L2).  Inside a k-step the k order is permuted (a sum may be taken
-// in any order; the order is the same in every k-step and every run): lane
+// A k-step covers 64 consecutive k: one 32 KB tile of M (hi and lo parts)
+// and one 32 KB chunk of q_n, both fetched one k-step ahead.  M is read once
+// per step, so its loads are non-temporal (they do not evict q_n from L2).  Inside a
+// k-step the k order is permuted (a sum may be taken in any order): lane
 // group g owns k = 16 g + 8 t + (0..7) in substep t = 0, 1, so its B
 // fragment is q-chunk block 2 g + t.
 template <int RT>
@@ -130,29 +129,16 @@ __global__ __launch_bounds__(256, 2) void gemm_bf16x3_kernel(const DenseGemmArgs
 
     constexpr int PER_THREAD = (CHUNK + 255) / 256;
     u32x4 rq[PER_THREAD];
-    // M fragments rotate through three register sets: while one is multiplied
-    // the next two k-steps' tiles are in flight (two 32 KB tiles per
-    // workgroup, enough outstanding loads to cover HBM latency with two
-    // workgroups per CU).  The MFMAs read a set in place, so no copy of a
-    // register still being loaded forces an early wait.
-    u32x4 ra0[8], ra1[8], ra2[8];  // [row 0/1][hi/lo][substep 0/1]
-    // Fetches past the last k-step re-read the last tile (a few per cent more
-    // requests, served from cache) so that every k-step issues the same loads:
-    // with no branch around them the wait counts stay exact.
-    auto fetch_m = [&](u32x4 (&ra)[8], int J) {
-        const u32x4* src = mt + int64_t(J < nsteps ? J : nsteps - 1) * TILE;
-#pragma unroll
-        for (int u = 0; u < 8; ++u) ra[u] = __builtin_nontemporal_load(src + u * 64);
-    };
-    auto fetch_q = [&](int J) {
-        gather_chunk<u32x4, CHUNK, PER_THREAD>(rq, qsrc + ((kbeg + int64_t(J < nsteps ? J : nsteps - 1) * KS) / 8) * R * 2);
-    };
-    // one k-step j with M fragments `cur`: stage q's chunk (fetched one step
-    // ahead) into LDS, fetch q for step j + 1 and M for step j + 2 into `nxt2`
-    // (the set step j - 1 used), then multiply.  q goes first: loads complete
-    // in issue order as far as the wait counter is concerned, so step j + 1
-    // can wait for its q chunk while step j + 2's M tile is still in flight.
-    auto kstep = [&](int j, const u32x4 (&cur)[8], u32x4 (&nxt2)[8]) {
+    u32x4 ra[8];  // [row 0/1][hi/lo][substep 0/1]
+#define FTH_BF16_FETCH(J)                                                          \
+    {                                                                              \
+        const int64_t kf = kbeg + int64_t(J) * KS;                                 \
+        gather_chunk<u32x4, CHUNK, PER_THREAD>(rq, qsrc + (kf / 8) * R * 2);       \
+        const u32x4* src = mt + int64_t(J) * TILE;                                 \
+        _Pragma("unroll") for (int u = 0; u < 8; ++u) ra[u] = __builtin_nontemporal_load(src + u * 64); \
+    }
+    FTH_BF16_FETCH(0)
+    for (int j = 0; j < nsteps; ++j) {
         u32x4* buf = qs[j & 1];
         // staged planar, [hi|lo][k/8][R], so the B reads below are 16 contiguous
         // bytes per lane (no bank conflicts)
@@ -161,8 +147,10 @@ __global__ __launch_bounds__(256, 2) void gemm_bf16x3_kernel(const DenseGemmArgs
             const int idx = int(threadIdx.x) + 256 * u;
             if (CHUNK % 256 == 0 || idx < CHUNK) buf[(idx & 1) * (CHUNK / 2) + (idx >> 1)] = rq[u];
         }
-        fetch_q(j + 1);
-        fetch_m(nxt2, j + 2);
+        bf16x8 a[8];
+#pragma unroll
+        for (int u = 0; u < 8; ++u) a[u] = __builtin_bit_cast(bf16x8, ra[u]);
+        if (j + 1 < nsteps) FTH_BF16_FETCH(j + 1)
         __syncthreads();
 #pragma unroll
         for (int t = 0; t < 2; ++t)
@@ -171,28 +159,16 @@ __global__ __launch_bounds__(256, 2) void gemm_bf16x3_kernel(const DenseGemmArgs
                 const u32x4* bsrc = buf + (2 * lg + t) * R + 16 * c + lr;
                 const bf16x8 bhi = __builtin_bit_cast(bf16x8, bsrc[0]);
                 const bf16x8 blo = __builtin_bit_cast(bf16x8, bsrc[CHUNK / 2]);
-                // row tile 0: cur[0 + t] (hi), cur[2 + t] (lo); row tile 1: cur[4 + t], cur[6 + t]
-                const bf16x8 a0h = __builtin_bit_cast(bf16x8, cur[0 + t]), a1h = __builtin_bit_cast(bf16x8, cur[4 + t]);
-                const bf16x8 a0l = __builtin_bit_cast(bf16x8, cur[2 + t]), a1l = __builtin_bit_cast(bf16x8, cur[6 + t]);
-                acc[0][c] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(a0h, bhi, acc[0][c], 0, 0, 0);
-                acc[1][c] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(a1h, bhi, acc[1][c], 0, 0, 0);
-                acc[0][c] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(a0h, blo, acc[0][c], 0, 0, 0);
-                acc[1][c] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(a1h, blo, acc[1][c], 0, 0, 0);
-                acc[0][c] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(a0l, bhi, acc[0][c], 0, 0, 0);
-                acc[1][c] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(a1l, bhi, acc[1][c], 0, 0, 0);
+                // row tile 0: a[0 + t] (hi), a[2 + t] (lo); row tile 1: a[4 + t], a[6 + t]
+                acc[0][c] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(a[0 + t], bhi, acc[0][c], 0, 0, 0);
+                acc[1][c] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(a[4 + t], bhi, acc[1][c], 0, 0, 0);
+                acc[0][c] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(a[0 + t], blo, acc[0][c], 0, 0, 0);
+                acc[1][c] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(a[4 + t], blo, acc[1][c], 0, 0, 0);
+                acc[0][c] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(a[2 + t], bhi, acc[0][c], 0, 0, 0);
+                acc[1][c] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(a[6 + t], bhi, acc[1][c], 0, 0, 0);
             }
-    };
-    fetch_q(0);
-    fetch_m(ra0, 0);
-    fetch_m(ra1, 1);
-    int j = 0;
-    for (; j + 3 <= nsteps; j += 3) {
-        kstep(j, ra0, ra2);
-        kstep(j + 1, ra1, ra0);
-        kstep(j + 2, ra2, ra1);
     }
-    if (j < nsteps) kstep(j, ra0, ra2);
-    if (j + 1 < nsteps) kstep(j + 1, ra1, ra0);
+#undef FTH_BF16_FETCH
     float* part = static_cast<float*>(g.part) + int64_t(ks) * P * R;
 #pragma unroll
     for (int t = 0; t < 2; ++t)
