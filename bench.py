@@ -531,6 +531,17 @@ def profile_summary(d: str, workload_name: str) -> str:
     kind, names, unit_steps = unit_of(kname)
     with open(os.path.join(d, "kt", "kt_kernel_stats.csv")) as fh:
         stats = list(csv.DictReader(fh))
+    # per-dispatch durations; the timed region is the last steps / unit_steps launches (the
+    # statistics' average also holds the autotuner's trial launches and the warm-up)
+    with open(os.path.join(d, "kt", "kt_kernel_trace.csv")) as fh:
+        trace = list(csv.DictReader(fh))
+    n_timed = max(1, int(bench_line["steps"]) // unit_steps)
+
+    def timed_avg_ns(nm):
+        ds = sorted((int(r["Start_Timestamp"]), int(r["End_Timestamp"]) - int(r["Start_Timestamp"]))
+                    for r in trace if nm in r["Kernel_Name"])
+        ds = [x[1] for x in ds[-n_timed:]]
+        return (sum(ds) / len(ds), len(ds)) if ds else (float("nan"), 0)
     cf, cw = pmc("fetch_copy"), pmc("write_copy")
     copy_key = max((k for k in cf if "elementwise" in k), key=lambda k: len(cf[k]["FETCH_SIZE"]))
     copy_bytes = float(1 << 30)
@@ -552,18 +563,19 @@ def profile_summary(d: str, workload_name: str) -> str:
                      f"{float(r['MaxNs']) / 1e3:9.2f} {float(r['Percentage']):6.2f}")
     lines += ["", f"counter scale from the copy kernel ({copy_key.split('(')[0][:60]}..., 1 GiB read + 1 GiB written):",
               f"  FETCH_SIZE x {fscale:.3f}, WRITE_SIZE x {wscale:.3f}", "",
-              "per dispatch of the unit's kernels (median over dispatches):"]
+              f"per dispatch of the unit's kernels (time: mean over the timed region's last {n_timed} dispatches "
+              "in the kernel trace; counters: median over dispatches):"]
     avg_ns, fetch_b, write_b = 0.0, 0.0, 0.0
     valu_busy, valu_insts, mfma_busy = None, None, None
     for nm in names:
-        st = [r for r in stats if nm in r["Name"]]
-        a = float(st[0]["AverageNs"]) if st else float("nan")
+        a, cnt = timed_avg_ns(nm)
         f_raw = med(fe, nm, "FETCH_SIZE")
         w_raw = med(wr, nm, "WRITE_SIZE")
         avg_ns += a
         fetch_b += f_raw * 1024 * fscale
         write_b += w_raw * 1024 * wscale
-        lines.append(f"  {nm}: avg {a / 1e3:.2f} us, FETCH_SIZE {f_raw:.0f} KiB -> {f_raw * 1024 * fscale / 1e6:.1f} MB, "
+        lines.append(f"  {nm}: avg {a / 1e3:.2f} us over {cnt}, FETCH_SIZE {f_raw:.0f} KiB -> "
+                     f"{f_raw * 1024 * fscale / 1e6:.1f} MB, "
                      f"WRITE_SIZE {w_raw:.0f} KiB -> {w_raw * 1024 * wscale / 1e6:.1f} MB")
         if va is not None and nm == names[0]:
             act = med(va, nm, "SQ_ACTIVE_INST_VALU")
