@@ -128,6 +128,28 @@ def test_autotuner_may_block_and_keeps_trajectory():
         assert np.allclose(x, y, rtol=1e-12, atol=0)
 
 
+def test_autotuner_cache_distinguishes_estimators():
+    """Two tuned contexts of the same shape in one process, the first with
+    position-form accumulators only and the second also with the momentum
+    form and traces (which change the eligible blocked shapes): the second
+    must not reuse a shape it cannot launch, and both reproduce the one-step
+    kernel."""
+    g = fi.load_gle("fermi_b20_ns4")
+    M, h = banded(200_003, 78, fth.FTH_FP32)
+    base = dict(pairs=fi.random_pairs(M.n, 64, 2), replicas=32, seed=5, acc_diag=True, block_len=10)
+    for extra in (dict(), dict(acc_pp=True, acc_trace=True), dict()):
+        kw = dict(base, **extra)
+        a = fth.Solver(M, g.A_p, g.C_p, h, tune=True, **kw).run(40)
+        b = fth.Solver(M, g.A_p, g.C_p, h, temporal_steps=-1, **kw).run(40)
+        print(f"[tune {sorted(extra)}] {a.kernel_name}", flush=True)
+        for x, y in zip(a.state(), b.state()):
+            assert np.array_equal(x, y)
+        for x, y in zip(a.accumulators()[:3], b.accumulators()[:3]):
+            assert np.allclose(x, y, rtol=1e-12, atol=0)   # traces: FP64 sums tiled differently
+        a.close()
+        b.close()
+
+
 @pytest.mark.parametrize("persistent", [0, -1], ids=["persistent", "per-tile"])
 def test_blocked_full_size_bit_identical(persistent):
     """Banded N = 1e6, R = 32 in the launch shape the benchmark's autotuner
