@@ -89,7 +89,8 @@ def workload(name: str) -> dict:
         # the paper's M1 (logarithm example): periodic 24^3 lattice, on-site 100, hopping U[0, 2]
         # to the first six neighbour shells (81 entries per row); log det M = Tr ln M as the
         # kinetic trace sum_i <p_i^2> with the momentum-form ln GLE (Eq. 7; omega in [e, 100 e],
-        # which holds M1's spectrum without a map)
+        # which holds M1's spectrum without a map); the first 2000 steps (the warm-up of a
+        # --warmup 2000 run) are burn-in, so the estimate leaves out the transient from q = p = 0
         M = fi.m1_lattice_csr(24, 6006, dtype=np.float32)
         g = fi.load_gle("ln_p_ns8")
         _, hi = fth.fth_gershgorin(M)
@@ -98,7 +99,7 @@ def workload(name: str) -> dict:
                        "estimates": "diagonal + 1024 pairs, position and momentum forms, traces",
                        "steps_in_config": 20000},
                  M=M, g=g, h=0.1 / np.sqrt(hi), R=32, pairs=fi.random_pairs(M.n, 1024, 6007), prec=fth.FTH_FP32,
-                 steps=20000, extra=dict(acc_pp=True, acc_trace=True))
+                 steps=20000, extra=dict(acc_pp=True, acc_trace=True, burn_in=2000))
     elif name == "m2-exp":
         # the paper's M2 (exponential example): dense, eigenvalues in (-300, 300) by Gerschgorin;
         # Tr exp(-M / 100) with the exp(-x) GLE on M' = M / 100 + 3.1 I
