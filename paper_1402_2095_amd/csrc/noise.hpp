@@ -48,8 +48,10 @@ __device__ __forceinline__ Block4 philox4x32_10(uint32_t c0, uint32_t c1, uint32
 // u = (2 (x >> 9) + 1) 2^-24 in FP32 without a conversion: the top 23 bits
 // as the mantissa of a float in [1, 2) give 1 + (x >> 9) 2^-23, and
 // subtracting 1 - 2^-24 is exact (Sterbenz: both operands lie in [1/2, 2]).
+// The bit pattern 0x3f800000 | (x >> 9) is the low word of the 64-bit value
+// {0x7f, x} shifted right by 9: one v_alignbit_b32 instead of a shift and an or.
 __device__ __forceinline__ float uniform_f32(uint32_t x) {
-    return __uint_as_float((x >> 9) | 0x3f800000u) - 0x1.fffffep-1f;
+    return __uint_as_float(__builtin_amdgcn_alignbit(0x7fu, x, 9u)) - 0x1.fffffep-1f;
 }
 
 // Box-Muller in FP32 with the hardware transcendental unit: v_log_f32 is
