@@ -22,7 +22,7 @@ from oracle import exact
 
 POSITION = ["invsqrt_ns4", "fermi_b20_ns4", "fermi_b5_ns4", "ln_ns4", "expneg_ns4", "invsqrt_ns4_h05"]
 MOMENTUM = ["ln_p_ns8", "ln_p_ns10", "expneg_p_ns4", "expneg_p_ns6", "expneg_p_ns8", "expneg_p_ns10"]
-GAP = ["fermi_gap_p_ns4", "fermi_gap_p_ns6", "fermi_gap_p_ns8"]
+GAP = ["fermi_gap_p_ns4", "fermi_gap_p_ns6", "fermi_gap_p_ns8", "fermi_gap_p_ns10"]
 SMOOTH = {"invsqrt": lambda x: x ** -0.5, "ln": np.log, "expneg": lambda x: np.exp(-x)}
 
 
