@@ -652,7 +652,7 @@ def main():
         print(text)
         return
     if args.gpus != 1:
-        print("bench.py: this build runs on one GPU only (it has no multi-GPU path); --gpus must be 1",
+        print("bench.py: the library runs on one GPU (it has no multi-GPU path); --gpus must be 1",
               file=sys.stderr)
         sys.exit(2)
     import torch

@@ -66,7 +66,7 @@ typedef enum {
     FTH_ESTATE = -4,         /* call not valid in the context's current state */
     FTH_ENONFINITE = -5,     /* the dynamics produced a non-finite value; the
                                 context is poisoned (M not SPD or h too large) */
-    FTH_EUNSUPPORTED = -6    /* valid request this build does not implement */
+    FTH_EUNSUPPORTED = -6    /* valid request the library does not implement */
 } fth_status;
 
 typedef enum { FTH_DENSE = 0, FTH_CSR = 1 } fth_format;
