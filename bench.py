@@ -122,13 +122,13 @@ def workload(name: str) -> dict:
 
 # --------------------------------------------------- algorithmic figures
 def step_bytes(w: dict) -> float:
-    """Bytes one time step must move at minimum (per replica-dof figure x
-    N R, as derived for the scope table): the state q, p, s_1..s_ns read and
-    written once; sparse: the CSR matrix once (32-bit row pointers, 32-bit
-    column indices, one value per nonzero) and the FP64 diagonal block
-    accumulator (and its momentum-form twin, when kept) read and written;
-    dense: M once as bf16 hi + lo (4 bytes per entry; FP64: 8).  Selected
-    pairs are negligible and left out."""
+    """Bytes one time step must move at minimum (a per replica-dof figure
+    times N R): the state q, p, s_1..s_ns read and written once; sparse: the
+    CSR matrix once (32-bit row pointers, 32-bit column indices, one value
+    per nonzero) and the FP64 diagonal block accumulator (and its
+    momentum-form twin, when kept) read and written; dense: M once as bf16
+    hi + lo (4 bytes per entry; FP64: 8).  Selected pairs are negligible and
+    left out."""
     from paper_1402_2095_amd import fth
     b = 8 if w["prec"] == fth.FTH_FP64 else 4
     n, R, ns = w["n"], w["R"], w["g"].ns
