@@ -122,9 +122,10 @@ struct DenseGemmArgs {
 // Largest workgroup of the temporally blocked step: a row's (p, s) and CSR
 // entries stay in registers for the whole launch, so larger NS (and FP64)
 // need the register file of fewer threads.
-// Momentum-form and trace accumulators (xtra) need a few more registers:
-// with them, 1024 threads only for FP32 at ns <= 4 (a few more spilled
-// registers, reloaded once per tile).
+// Momentum-form and trace accumulators (xtra) need more registers: with
+// them, 1024 threads only for FP32 at ns <= 4, where the compiler spills
+// some of the row's data and reloads it each step (correct, but slower than
+// the one-step kernel on the banded shapes measured).
 constexpr int tb_max_block(bool f64, int ns, bool xtra = false) {
     const int b = f64 ? (ns == 0 ? 1024 : ns <= 4 ? 512 : 256) : (ns <= 4 ? 1024 : ns <= 9 ? 512 : 256);
     return xtra && b > 512 && (f64 || ns > 4) ? 512 : b;
