@@ -106,18 +106,20 @@ def test_m1_log_det_via_ln_target_and_trace():
     assert abs(ref_h - exact_ld) <= bound
 
 
-def test_m1_log_det_via_momentum_form():
+@pytest.mark.parametrize("n_side,gle", [(6, "ln_p_ns8"), (10, "ln_p_ns8"), (10, "ln_p_ns10")])
+def test_m1_log_det_via_momentum_form(n_side, gle):
     """log det M1 the way the paper estimates it (Eq. 7 and the Sec. II
-    examples): a GLE fitted so that <p^2>(omega) = ln omega^2 over
-    omega in [e, 100 e], eight extra momenta, no rescaling needed since M1's
-    spectrum [85, 180] sits inside the window.  log det M = Tr ln M is the
-    kinetic trace sum_i <p_i^2>.  Statistical parity against the exact
-    momentum response of the integrated step, sum_k gh_p(lambda_k); the model
-    error (fit + step) against slogdet stays within the fit report."""
-    g = fi.load_gle("ln_p_ns8")
+    examples, which compare lattices of several sizes): a GLE fitted so that
+    <p^2>(omega) = ln omega^2 over omega in [e, 100 e], eight or ten extra
+    momenta, no rescaling needed since M1's spectrum (about [80, 190]) sits
+    inside the window.  log det M = Tr ln M is the kinetic trace
+    sum_i <p_i^2>.  Statistical parity against the exact momentum response
+    of the integrated step, sum_k gh_p(lambda_k); the model error (fit +
+    step) against slogdet stays within the fit report."""
+    g = fi.load_gle(gle)
     assert g.meta["form"] == "p"
     lo_w, hi_w = g.meta["window_lambda"]
-    M = fi.m1_lattice_csr(6, 3)
+    M = fi.m1_lattice_csr(n_side, 3)
     n = M.n
     lam = np.linalg.eigvalsh(csr_to_dense(M))
     assert lo_w <= lam.min() and lam.max() <= hi_w
@@ -134,7 +136,7 @@ def test_m1_log_det_via_momentum_form():
     exact_ld = float(np.sum(np.log(lam)))
     assert exact_ld == pytest.approx(float(np.linalg.slogdet(csr_to_dense(M))[1]), rel=1e-12)
     z = (logdet - ref_h) / se_ld
-    print(f"[M1 logdet p-form] est {logdet:.3f} +- {se_ld:.3f}, exact response {ref_h:.3f}, "
+    print(f"[M1 logdet p-form {n_side}^3 {gle}] est {logdet:.3f} +- {se_ld:.3f}, exact response {ref_h:.3f}, "
           f"slogdet {exact_ld:.3f}, z {z:.2f}", flush=True)
     assert abs(z) < 5.0
     # the per-row diagonal <p_i^2> sums to the trace output
