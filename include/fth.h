@@ -400,6 +400,13 @@ typedef struct {
        (pairs (i, i) count as diagonal entries); -1 returns them as run. */
     double scale_r, scale_m, gle_alpha, gle_gamma;
     int32_t unscale_target;
+    /* != 0: the request's estimates are the momentum form <p_i p_j> of Eq. 7
+       (acc_pp; for a GLE fitted so that <p^2>(omega) = f(omega^2)) instead
+       of <q_i q_j>.  Its stop test, results and unscaling use that block
+       (the momentum response scales as gamma g_p(M' / alpha^2), so the
+       results are multiplied by alpha^-2 before fth_unscale).  Packs like
+       any other request. */
+    int32_t momentum_form;
 } fth_request;
 
 typedef enum {

@@ -49,6 +49,7 @@ struct SrvRequest {
     double target = 0;
     int64_t max_steps = 0;
     int32_t unscale_target = -1;
+    bool momentum = false;            // report the <p p> block (acc_pp) instead of <q q>
     std::vector<double> kind_weight;  // 1 for a pair (i, i), else 0 (for fth_unscale)
     std::vector<int64_t> di, dj;      // output index of (i,i) and (j,j) for each pair, or -1
     // run state
@@ -232,13 +233,27 @@ fth_status group_graph(Group& g, int64_t K, hipGraphExec_t* out) {
     return FTH_OK;
 }
 
+// The estimates a request reports: its pairs, from the <q q> block or, for a
+// momentum-form request, the <p p> block that follows it.
+fth_status read_reported(const SrvRequest* r, std::vector<double>& est, std::vector<double>& se, int64_t* nacc) {
+    const int64_t no = fth_num_outputs(r->ctx);
+    const int64_t np = r->info.n_out;
+    std::vector<double> e(static_cast<size_t>(no)), v(static_cast<size_t>(no));
+    fth_status st = fth_read(r->ctx, e.data(), v.data(), no, nacc);
+    if (st != FTH_OK) return st;
+    const int64_t off = r->momentum ? np : 0;
+    if (off + np > no) return fail(FTH_ESTATE, "request has fewer outputs than it reports");
+    est.assign(e.begin() + off, e.begin() + off + np);
+    se.assign(v.begin() + off, v.begin() + off + np);
+    return FTH_OK;
+}
+
 // Retire a request: read its results, release its context and memory.
 void finish(fth_server* s, SrvRequest* r, int32_t state, fth_status st) {
     if (r->ctx) {
-        const int64_t no = fth_num_outputs(r->ctx);
-        r->est.assign(size_t(no), 0.0);
-        r->se.assign(size_t(no), 0.0);
-        if (state == FTH_REQ_DONE) (void)fth_read(r->ctx, r->est.data(), r->se.data(), no, nullptr);
+        r->est.assign(size_t(r->info.n_out), 0.0);
+        r->se.assign(size_t(r->info.n_out), 0.0);
+        if (state == FTH_REQ_DONE) (void)read_reported(r, r->est, r->se, nullptr);
         fth_destroy(r->ctx);  // waits for its stream
         r->ctx = nullptr;
         s->reserved -= r->info.footprint;
@@ -298,10 +313,9 @@ double max_rel_stderr(const SrvRequest& r, const std::vector<double>& est, const
 
 // At a check boundary: read the stderr summary and retire at the target or cap.
 void check(fth_server* s, SrvRequest* r) {
-    const int64_t no = fth_num_outputs(r->ctx);
-    std::vector<double> est(static_cast<size_t>(no)), se(static_cast<size_t>(no));
+    std::vector<double> est, se;
     int64_t nacc = 0;
-    fth_status st = fth_read(r->ctx, est.data(), se.data(), no, &nacc);
+    fth_status st = read_reported(r, est, se, &nacc);
     if (st != FTH_OK) {
         finish(s, r, FTH_REQ_FAILED, st);
         return;
@@ -555,6 +569,8 @@ fth_status fth_server_submit(fth_server* s, const fth_request* q, uint64_t* id) 
     r->opt.gle_gamma = q->gle_gamma;
     if (q->unscale_target < -1 || q->unscale_target > FTH_TARGET_EXPNEG) return fail(FTH_EINVAL, "unknown unscale target");
     r->unscale_target = q->unscale_target;
+    r->momentum = q->momentum_form != 0;
+    r->opt.acc_pp = r->momentum ? 1 : 0;
     r->target = q->target_rel_stderr;
     r->max_steps = q->max_steps;
     // normalisation of off-diagonal estimates by the request's own diagonals
@@ -578,7 +594,9 @@ fth_status fth_server_submit(fth_server* s, const fth_request* q, uint64_t* id) 
     std::vector<double> T, S;
     st = make_propagator(&r->gle, r->dt, T, S);
     if (st != FTH_OK) return st;
-    r->info.footprint = fth_footprint_bytes(&r->M, r->gle.ns, r->opt.replicas, q->npairs, 0, r->opt.precision);
+    // (a momentum-form request keeps a second set of accumulators: counted as twice the pairs)
+    r->info.footprint = fth_footprint_bytes(&r->M, r->gle.ns, r->opt.replicas, q->npairs * (r->momentum ? 2 : 1), 0,
+                                            r->opt.precision);
     if (r->info.footprint > s->opt.hbm_budget)
         return fail(FTH_ENOMEM, "request footprint %zu exceeds the server budget %zu", r->info.footprint,
                     s->opt.hbm_budget);
@@ -648,7 +666,7 @@ fth_status fth_server_result(fth_server* s, uint64_t id, double* est, double* se
         }
     }
     if (r->ctx) {
-        fth_status st = fth_read(r->ctx, e.data(), v.data(), r->info.n_out, nullptr);
+        fth_status st = read_reported(r, e, v, nullptr);
         if (st != FTH_OK) return st;
     } else {
         if (r->info.state != FTH_REQ_DONE) return fail(FTH_ESTATE, "request has no result");
@@ -656,6 +674,15 @@ fth_status fth_server_result(fth_server* s, uint64_t id, double* est, double* se
         v = r->se;
     }
     if (r->unscale_target >= 0) {
+        if (r->momentum && r->opt.gle_alpha != 0.0 && r->opt.gle_alpha != 1.0) {
+            // fth_unscale undoes the position prefactor gamma / alpha^2; the momentum
+            // response carries gamma alone
+            const double a2 = 1.0 / (r->opt.gle_alpha * r->opt.gle_alpha);
+            for (size_t k = 0; k < e.size(); ++k) {
+                e[k] *= a2;
+                v[k] *= a2;
+            }
+        }
         fth_status st = fth_unscale(r->unscale_target, r->opt.scale_r == 0 ? 1.0 : r->opt.scale_r, r->opt.scale_m,
                                     r->opt.gle_alpha == 0 ? 1.0 : r->opt.gle_alpha,
                                     r->opt.gle_gamma == 0 ? 1.0 : r->opt.gle_gamma, r->info.n_out,

@@ -103,7 +103,8 @@ class fth_request(ctypes.Structure):
                 ("seed", ctypes.c_uint64), ("stream_id", ctypes.c_uint32), ("burn_in", ctypes.c_int64),
                 ("block_len", ctypes.c_int64), ("target_rel_stderr", ctypes.c_double), ("max_steps", ctypes.c_int64),
                 ("scale_r", ctypes.c_double), ("scale_m", ctypes.c_double), ("gle_alpha", ctypes.c_double),
-                ("gle_gamma", ctypes.c_double), ("unscale_target", ctypes.c_int32)]
+                ("gle_gamma", ctypes.c_double), ("unscale_target", ctypes.c_int32),
+                ("momentum_form", ctypes.c_int32)]
 
 
 class fth_request_info(ctypes.Structure):
@@ -472,13 +473,14 @@ class Server:
 
     def submit(self, M, A_p, C_p, dt, pairs, replicas=0, precision=FTH_FP32, seed=0, stream_id=0, burn_in=0,
                block_len=0, target=1e-2, max_steps=0, scale_r=1.0, scale_m=0.0, gle_alpha=1.0, gle_gamma=1.0,
-               unscale_target=-1) -> int:
+               unscale_target=-1, momentum_form=False) -> int:
         m = _Matrix(M)
         g, keep = _gle_struct(A_p, C_p)
         pr = np.ascontiguousarray(pairs, dtype=np.int32).reshape(-1, 2)
         q = fth_request(m.struct, g, float(dt), pr.ctypes.data, len(pr), int(replicas), int(precision), int(seed),
                         int(stream_id), int(burn_in), int(block_len), float(target), int(max_steps),
-                        float(scale_r), float(scale_m), float(gle_alpha), float(gle_gamma), int(unscale_target))
+                        float(scale_r), float(scale_m), float(gle_alpha), float(gle_gamma), int(unscale_target),
+                        int(bool(momentum_form)))
         rid = ctypes.c_uint64()
         _check(lib().fth_server_submit(self.h, ctypes.byref(q), ctypes.byref(rid)))
         return int(rid.value)

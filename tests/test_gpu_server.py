@@ -1,8 +1,9 @@
 """GPU tests of the serving layer: continuous batching with the packed
 multi-request kernel, admission by device footprint, stopping at a target
-standard error, cancellation; and a request's result is the same alone and
-in the mix (bit for bit: the packed kernel runs the same per-row arithmetic,
-with the request's own noise stream and step counter)."""
+standard error, cancellation, spectral maps and the momentum estimator; and
+a request's result is the same alone and in the mix (bit for bit: the packed
+kernel runs the same per-row arithmetic, with the request's own noise stream
+and step counter)."""
 import numpy as np
 import pytest
 
@@ -266,3 +267,51 @@ def test_failed_admission_does_not_stop_the_others():
     run_to_done(srv, [ib, ig])
     assert srv.poll(ib)["state"] == fth.FTH_REQ_FAILED and srv.poll(ib)["status"] == fth.FTH_EUNSUPPORTED
     assert srv.poll(ig)["state"] == fth.FTH_REQ_DONE and srv.poll(ig)["steps"] == 100
+
+
+def test_momentum_form_requests():
+    """Requests for the paper's momentum estimator (Eq. 7): results are the
+    <p p> block of a standalone context with acc_pp, bit for bit, packed beside
+    a position-form request; with a spectral map (r, alpha, gamma) and the ln
+    target, the momentum prefactor (gamma, not gamma / alpha^2) is undone."""
+    g = fi.load_gle("ln_p_ns8")
+    M = fi.m1_lattice_csr(8, 95)
+    _, hi = fth.fth_gershgorin(M)
+    h = 0.1 / np.sqrt(hi)
+    pairs = request_pairs(M.n, 96)
+    x = dict(M=M, A_p=g.A_p, C_p=g.C_p, dt=h, pairs=pairs, seed=96, stream_id=11)
+    y = lap_request(10, 97, 12)      # a position-form request packed with it
+    r, alpha, gamma = 2.0, 1.3, 0.8
+    srv = fth.Server(steps_per_tick=100)
+    common = dict(block_len=50, max_steps=600, target=0.0)
+    ids = [srv.submit(**x, **common, momentum_form=True),
+           srv.submit(**x, **common, momentum_form=True, scale_r=r, gle_alpha=alpha, gle_gamma=gamma,
+                      unscale_target=fth.FTH_TARGET_LN),
+           srv.submit(**y, **common)]
+    run_to_done(srv, ids)
+    infos = [srv.poll(i) for i in ids]
+    assert all(i["state"] == fth.FTH_REQ_DONE and i["steps"] == 600 for i in infos)
+    assert infos[0]["packed"] == 1 and infos[2]["packed"] == 1
+    n_out = len(pairs)
+    # plain momentum request
+    est, se = srv.result(ids[0])
+    sol = fth.Solver(M, g.A_p, g.C_p, h, pairs=pairs, replicas=32, seed=96, stream_id=11, block_len=50,
+                     acc_pp=True).run(600)
+    e0, s0, _ = sol.read()
+    assert np.array_equal(est, e0[n_out:]) and np.array_equal(se, s0[n_out:])
+    # mapped momentum request: p block times alpha^-2, then the ln identity
+    est, se = srv.result(ids[1])
+    sol = fth.Solver(M, g.A_p, g.C_p, h, pairs=pairs, replicas=32, seed=96, stream_id=11, block_len=50, acc_pp=True,
+                     scale_r=r, gle_alpha=alpha, gle_gamma=gamma).run(600)
+    e1, s1, _ = sol.read()
+    w = (pairs[:, 0] == pairs[:, 1]).astype(np.float64)
+    a2 = 1.0 / (alpha * alpha)
+    ep, sp = e1[n_out:] * a2, s1[n_out:] * a2
+    eu, su = fth.fth_unscale(fth.FTH_TARGET_LN, r, 0.0, alpha, gamma, w, ep, sp)
+    assert np.array_equal(est, eu) and np.array_equal(se, su)
+    # both estimate ln M: the diagonal agrees between the two within their errors and the model error
+    d = w > 0
+    e_plain, s_plain = srv.result(ids[0])
+    z = (est[d] - e_plain[d]) / np.sqrt(se[d] ** 2 + s_plain[d] ** 2)
+    print(f"[serve p-form] mapped vs plain diagonal of ln M: max|z| {np.max(np.abs(z)):.2f}", flush=True)
+    assert np.max(np.abs(z)) < 6.0 or np.max(np.abs(est[d] / e_plain[d] - 1)) < 0.03
