@@ -21,13 +21,14 @@ pytestmark = pytest.mark.gpu
 DELTA, HOP, SHIFT = 1.2, 0.9797958971132712, 6.1
 
 
-@pytest.mark.parametrize("name", ["fermi_gap_p_ns4"])
-def test_insulator_occupation_and_sublattice_densities(name):
+@pytest.mark.parametrize("name,prec", [("fermi_gap_p_ns4", fth.FTH_FP32), ("fermi_gap_p_ns6", fth.FTH_FP64)],
+                         ids=["ns4-fp32", "ns6-fp64"])
+def test_insulator_occupation_and_sublattice_densities(name, prec):
     g = fi.load_gle(name)
     t = g.meta["target"]
     assert t["kind"] == "fermi_gap" and t["mu"] == SHIFT and t["gap"] == pytest.approx(2 * DELTA)
     n_side = 16
-    M = fi.insulator3d_csr(n_side, DELTA, HOP, SHIFT)
+    M = fi.insulator3d_csr(n_side, DELTA, HOP, SHIFT, dtype=np.float64 if prec == fth.FTH_FP64 else np.float32)
     n = M.n
     lam = exact.insulator_eigs(n_side, DELTA, HOP, SHIFT)
     lo_w, hi_w = g.meta["window_lambda"]
@@ -35,7 +36,7 @@ def test_insulator_occupation_and_sublattice_densities(name):
     h = fi.dt_rule(hi_w)
     # 58 blocks of 10^4 steps (about four of the slowest relaxation times each), so that the
     # per-site standard errors are well determined and max |z| over 4096 sites stays moderate
-    sol = fth.Solver(M, g.A_p, g.C_p, h, replicas=32, precision=fth.FTH_FP32, seed=41, burn_in=20000,
+    sol = fth.Solver(M, g.A_p, g.C_p, h, replicas=32, precision=prec, seed=41, burn_in=20000,
                      block_len=10000, acc_diag=True, acc_pp=True, acc_trace=True)
     sol.run(600000)
     est, se, _ = sol.read()
