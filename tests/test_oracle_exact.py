@@ -128,12 +128,27 @@ def test_gh_p_white_noise_closed_form():
         assert np.allclose(got, 1.7 / (1 - h * h * lam / 4), rtol=1e-10)
 
 
-def test_g0_p_is_omega_squared_times_g0():
-    """A stationary harmonic mode has d<q p>/dt = <p^2> - omega^2 <q^2> = 0, so
-    <p^2>(omega) = omega^2 <q^2>(omega) for any GLE (continuous time)."""
-    A, C = gle(4, 9)
+def test_g0_momentum_position_relation():
+    """Stationarity of <q p> for a harmonic mode under the GLE (continuous
+    time): q' = p, p' = -omega^2 q - A_pp p - sum_k A_{p s_k} s_k + noise, and
+    <q p> = 0 (from d<q^2>/dt = 0), give
+        <p^2> = omega^2 <q^2> + sum_k A_{p s_k} <q s_k>.
+    For an equilibrium GLE (C_p = kT I) both sides reduce to equipartition,
+    <p^2> = kT = omega^2 <q^2>; a colored-noise GLE fitted to a target has
+    <q s_k> != 0, so its momentum and position responses differ."""
     lam = np.geomspace(0.1, 12, 9)
-    assert np.allclose(exact.g0_p(lam, A, C), lam * exact.g0(lam, A, C), rtol=1e-9)
+    A, C = gle(4, 9)      # C = 1.1 I: equipartition
+    assert np.allclose(exact.g0_p(lam, A, C), 1.1, rtol=1e-9)
+    assert np.allclose(exact.g0(lam, A, C), 1.1 / lam, rtol=1e-9)
+    g = fth_inputs.load_gle("invsqrt_ns4")
+    for Ap, Cp in ((g.A_p, g.C_p), (A, C)):
+        for l in lam:
+            X = exact.g0_cov(float(l), Ap, Cp)     # order (q, p, s_1..s_ns)
+            assert abs(X[0, 1]) <= 1e-9 * np.sqrt(X[0, 0] * X[1, 1])
+            rhs = l * X[0, 0] + float(np.dot(Ap[0, 1:], X[0, 2:]))
+            assert X[1, 1] == pytest.approx(rhs, rel=1e-9)
+    # the fitted thermostat is far from equipartition at the low end of its window
+    assert exact.g0_p(np.array([0.1]), g.A_p, g.C_p)[0] > 2 * 0.1 * exact.g0(np.array([0.1]), g.A_p, g.C_p)[0]
 
 
 def test_gh_p_converges_to_g0_p_second_order():
