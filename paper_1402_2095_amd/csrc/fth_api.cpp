@@ -640,7 +640,7 @@ fth_status tb_select(fth_ctx* c, int KT, int block) {
     const bool xtra = c->opt.acc_pp || c->opt.acc_trace;
     const int E = block / (c->R / 4);
     const int T = E - 2 * KT * int(c->band_w);
-    const size_t lds = fth::tbp_lds_bytes(f64, c->ns, block, c->R, T, c->opt.acc_trace != 0);
+    const size_t lds = fth::tbp_lds_bytes(f64, c->ns, block, c->R, T, c->opt.acc_trace != 0, xtra);
     const int grid = f64 ? fth::tbp_resident_grid<double>(c->ns, KT, xtra, block, lds)
                          : fth::tbp_resident_grid<float>(c->ns, KT, xtra, block, lds);
     (void)hipGetLastError();  // an unsupported shape query leaves no sticky error behind

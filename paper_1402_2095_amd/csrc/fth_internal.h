@@ -167,9 +167,10 @@ constexpr int kTbpAuxWords = 3;
 
 // LDS bytes of the persistent blocked step for a workgroup of `block`
 // threads (4 replicas per thread): q of the extended rows twice, the trace
-// row sums (if kept) and each wave's staging area (state, slot rows and
-// bookkeeping of the next tile).
-constexpr size_t tbp_lds_bytes(bool f64, int ns, int block, int R, int T, bool traces) {
+// row sums (if kept), each wave's staging area (state, slot rows and
+// bookkeeping of the next tile) and, with the momentum or trace
+// accumulators (xtra), the extended rows' matrix values.
+constexpr size_t tbp_lds_bytes(bool f64, int ns, int block, int R, int T, bool traces, bool xtra) {
     const size_t rb = f64 ? 8 : 4;
     const size_t E = size_t(block) * 4 / size_t(R);
     const size_t q = 2 * E * size_t(R) * rb;
@@ -179,7 +180,8 @@ constexpr size_t tbp_lds_bytes(bool f64, int ns, int block, int R, int T, bool t
     const size_t sb = f64 ? sizeof(TbSlotRow<double>) : sizeof(TbSlotRow<float>);
     const size_t ci = (rows_per_wave * sb + 1023) / 1024;  // slot-row loads per wave
     const size_t stage = (size_t(block) / 64) * ((size_t(ns + 2) * vi + ci) * 1024 + size_t(kTbpAuxWords) * 256);
-    return q + tr + stage;
+    const size_t vals = xtra ? E * 8 * rb : 0;
+    return q + tr + stage + vals;
 }
 
 // One entry of the packed multi-request work list.

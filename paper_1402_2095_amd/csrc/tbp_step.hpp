@@ -96,6 +96,10 @@ __global__ __launch_bounds__(tb_max_block(sizeof(Real) == 8, NS, XTRA)) void tbp
     // per wave: NSI state loads, CI slot-row loads (1 KB each), AUX words (256 B each)
     char* wst = stage_base + wave * ((NSI + CI) * 1024 + AUX * 256);
     char* waux = wst + (NSI + CI) * 1024;
+    // with the momentum and trace accumulators the row's matrix values live in
+    // LDS for the tile ([E][8], shared by the row's lanes) instead of in eight
+    // registers per thread, which the extra accumulators need
+    Real* vlds = reinterpret_cast<Real*>(stage_base + (int(blockDim.x) >> 6) * ((NSI + CI) * 1024 + AUX * 256));
 
     // contiguous tile range of this workgroup; workgroups are dealt to the 8
     // XCDs round-robin, so those of one XCD get adjacent ranges
@@ -182,8 +186,12 @@ __global__ __launch_bounds__(tb_max_block(sizeof(Real) == 8, NS, XTRA)) void tbp
         for (int c = 0; c < NS; ++c) st.s[c] = stage_vec<Real, RPT>(wst, (2 + c) * VI, lane_t);
         const TbSlotRow<Real>* srow = reinterpret_cast<const TbSlotRow<Real>*>(wst + NSI * 1024 + (lane_t >> lg) * SB);
         Real dval[8];
+        if constexpr (XTRA) {
+            for (int u = rq; u < 8; u += tpr) vlds[e_t * 8 + u] = srow->val[u];
+        } else {
 #pragma unroll
-        for (int u = 0; u < 8; ++u) dval[u] = srow->val[u];
+            for (int u = 0; u < 8; ++u) dval[u] = srow->val[u];
+        }
         // column offsets stay packed (two registers) and are unpacked at use
         const uint64_t offs = *reinterpret_cast<const uint64_t*>(srow->off);
         const int nz = srow->nz;
@@ -202,14 +210,23 @@ __global__ __launch_bounds__(tb_max_block(sizeof(Real) == 8, NS, XTRA)) void tbp
             const bool close = acc_on && ((n - a.burn_in + 1) % a.block_len) == 0;
             const Real* cur = qlds + int64_t(s & 1) * E * R;
             Real* nxt = qlds + int64_t((s + 1) & 1) * E * R;
+            // the row index as the compiler must treat it in each step: the block
+            // sums' addresses are then formed where a block closes (rarely) instead
+            // of being kept live across the step loop
+            int64_t i_s = i;
+            asm volatile("" : "+v"(i_s));
+            // with the extra accumulators, the neighbour offsets are unpacked in each
+            // step (not once per tile into eight registers)
+            uint64_t offs_s = offs;
+            if constexpr (XTRA) asm volatile("" : "+v"(offs_s));
             if (output) {
                 if (a.dblk != nullptr) {
                     const double x = dot_row<Real, RPT>(st.q, st.q, tpr);
                     if (rq == 0 && acc_on) {
                         blk = blk + x;
                         if (close) {
-                            a.ds1[i] = a.ds1[i] + blk;
-                            a.ds2[i] = a.ds2[i] + blk * blk;
+                            a.ds1[i_s] = a.ds1[i_s] + blk;
+                            a.ds2[i_s] = a.ds2[i_s] + blk * blk;
                             blk = 0.0;
                         }
                     }
@@ -219,8 +236,8 @@ __global__ __launch_bounds__(tb_max_block(sizeof(Real) == 8, NS, XTRA)) void tbp
                     if (rq == 0 && acc_on) {
                         blkp = blkp + y;
                         if (close) {
-                            a.dp_s1[i] = a.dp_s1[i] + blkp;
-                            a.dp_s2[i] = a.dp_s2[i] + blkp * blkp;
+                            a.dp_s1[i_s] = a.dp_s1[i_s] + blkp;
+                            a.dp_s2[i_s] = a.dp_s2[i_s] + blkp * blkp;
                             blkp = 0.0;
                         }
                     }
@@ -239,10 +256,11 @@ __global__ __launch_bounds__(tb_max_block(sizeof(Real) == 8, NS, XTRA)) void tbp
 #pragma unroll
                 for (int u = 0; u < 8; ++u)
                     if (u < nz) {
-                        const int dc = int(int8_t(uint8_t(offs >> (8 * u))));
+                        const int dc = int(int8_t(uint8_t(offs_s >> (8 * u))));
                         const V qj = load_vec<Real, RPT>(cur + int64_t(e + dc) * R + r0);
+                        const Real mv = XTRA ? vlds[e * 8 + u] : dval[u];
 #pragma unroll
-                        for (int m = 0; m < RPT; ++m) acc[m] = fmaR(dval[u], qj.v[m], acc[m]);
+                        for (int m = 0; m < RPT; ++m) acc[m] = fmaR(mv, qj.v[m], acc[m]);
                     }
                 Real xi[NS + 1][RPT];
 #pragma unroll
@@ -340,7 +358,7 @@ int launch_tbp_step_impl(const StepArgs<Real>& a, const TbArgs<Real>& tb, const 
     if (fn == nullptr) return -2;
     const int block = tb.E << a.lg_tpr;
     if (block > tb_max_block(sizeof(Real) == 8, L.ns, x) || block % 64 != 0) return -3;
-    const size_t lds = tbp_lds_bytes(sizeof(Real) == 8, L.ns, block, a.R, tb.T, a.tpart != nullptr);
+    const size_t lds = tbp_lds_bytes(sizeof(Real) == 8, L.ns, block, a.R, tb.T, a.tpart != nullptr, x);
     StepArgs<Real> aa = a;
     TbArgs<Real> tt = tb;
     int kk = k;
