@@ -57,6 +57,12 @@ __global__ __launch_bounds__(tb_max_block(sizeof(Real) == 8, NS, XTRA)) void tb_
     RowState<Real, NS, RPT> st;
     int dcol[G];
     Real dval[G];
+    // with the extra accumulators the row's values live in LDS ([E][8], after q
+    // and the trace rows) and its column offsets in one packed register pair,
+    // which keeps the thread within the register budget without spills
+    Real* vlds = reinterpret_cast<Real*>(reinterpret_cast<char*>(qlds) + size_t(2) * E * R * sizeof(Real) +
+                                         (a.tpart != nullptr ? size_t(2) * T * 3 * sizeof(double) : 0));
+    uint64_t offs = 0;
     int nz = 0;
     double blk = 0.0, blkp = 0.0;
     int32_t pslot = -1;
@@ -69,10 +75,17 @@ __global__ __launch_bounds__(tb_max_block(sizeof(Real) == 8, NS, XTRA)) void tb_
         for (int c = 0; c < NS; ++c) st.s[c] = load_vec<Real, RPT>(psrow + (c + 1) * cs);
         const int64_t kb = a.row_ptr[i], ke = a.row_ptr[i + 1];
         nz = int(ke - kb);
+        if constexpr (XTRA) {
+            for (int u = rq; u < G; u += tpr) vlds[e * G + u] = u < nz ? a.val[kb + u] : Real(0);
 #pragma unroll
-        for (int u = 0; u < G; ++u) {
-            dcol[u] = u < nz ? int(a.col[kb + u] - i) : 0;
-            dval[u] = u < nz ? a.val[kb + u] : Real(0);
+            for (int u = 0; u < G; ++u)
+                offs |= uint64_t(uint8_t(int8_t(u < nz ? int(a.col[kb + u] - i) : 0))) << (8 * u);
+        } else {
+#pragma unroll
+            for (int u = 0; u < G; ++u) {
+                dcol[u] = u < nz ? int(a.col[kb + u] - i) : 0;
+                dval[u] = u < nz ? a.val[kb + u] : Real(0);
+            }
         }
         store_vec<Real, RPT>(qlds + int64_t(e) * R + r0, st.q);
         if (output && a.dblk != nullptr && rq == 0) blk = a.dblk[i];
@@ -129,12 +142,16 @@ __global__ __launch_bounds__(tb_max_block(sizeof(Real) == 8, NS, XTRA)) void tb_
             Real acc[RPT];
 #pragma unroll
             for (int m = 0; m < RPT; ++m) acc[m] = Real(0);
+            uint64_t offs_s = offs;
+            if constexpr (XTRA) asm volatile("" : "+v"(offs_s));   // unpacked in each step
 #pragma unroll
             for (int u = 0; u < G; ++u)
                 if (u < nz) {
-                    const V qj = load_vec<Real, RPT>(cur + int64_t(e + dcol[u]) * R + r0);
+                    const int dc = XTRA ? int(int8_t(uint8_t(offs_s >> (8 * u)))) : dcol[u];
+                    const V qj = load_vec<Real, RPT>(cur + int64_t(e + dc) * R + r0);
+                    const Real mv = XTRA ? vlds[e * G + u] : dval[u];
 #pragma unroll
-                    for (int m = 0; m < RPT; ++m) acc[m] = fmaR(dval[u], qj.v[m], acc[m]);
+                    for (int m = 0; m < RPT; ++m) acc[m] = fmaR(mv, qj.v[m], acc[m]);
                 }
             Real xi[NS + 1][RPT];
 #pragma unroll
@@ -236,7 +253,8 @@ int launch_tb_step_impl(const StepArgs<Real>& a, const TbArgs<Real>& tb, const S
     const int block = tb.E << a.lg_tpr;
     if (block > tb_max_block(sizeof(Real) == 8, L.ns, x) || block % 64 != 0) return -3;
     const size_t lds = size_t(2) * size_t(tb.E) * size_t(a.R) * sizeof(Real) +
-                       (a.tpart != nullptr ? size_t(2) * size_t(tb.T) * 3 * sizeof(double) : 0);
+                       (a.tpart != nullptr ? size_t(2) * size_t(tb.T) * 3 * sizeof(double) : 0) +
+                       (x ? size_t(tb.E) * 8 * sizeof(Real) : 0);
     StepArgs<Real> aa = a;
     TbArgs<Real> tt = tb;
     int kk = k;
