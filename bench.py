@@ -76,6 +76,16 @@ def workload(name: str) -> dict:
                  M=M, g=fi.load_gle("fermi_b20_ns4"), h=fi.dt_rule(fi.gershgorin_max(M)), R=32,
                  pairs=fi.random_pairs(M.n, 1024, 3004),
                  prec=fth.FTH_FP64 if name.endswith("fp64") else fth.FTH_FP32, steps=5000)
+    elif name == "banded1e6-pp":
+        # the same system with the paper's own estimator (Eq. 7): <p_i p_j> kept beside <q_i q_j>,
+        # with the momentum-form GLE of a zero-temperature Fermi step (same ns, so the same state)
+        M = fi.banded_spd_csr(1_000_000, 3003)
+        w.update(desc={"workload": "random banded SPD N=1e6, 7 nonzeros/row (CSR, FP32 values), momentum estimator",
+                       "gle": "ns=4, momentum-form Fermi step across a gap", "replicas": 32,
+                       "estimates": "diagonal + 1024 pairs, position and momentum forms", "steps_in_config": 5000},
+                 M=M, g=fi.load_gle("fermi_gap_p_ns4"), h=fi.dt_rule(fi.gershgorin_max(M)), R=32,
+                 pairs=fi.random_pairs(M.n, 1024, 3004), prec=fth.FTH_FP32, steps=5000,
+                 extra=dict(acc_pp=True))
     elif name in ("dense16384", "dense16384-fp64"):
         n = 16384
         M = fi.dense_ggt(n, 4004)
@@ -719,8 +729,8 @@ def main():
         sec = {}
         # warm-ups of about 0.2 s each: the inputs are generated on the host first, and a GPU left
         # idle meanwhile needs that long to return to full clocks
-        for name, st, wu in (("banded1e6-fp64", 100, 300), ("laplacian64", 1000, 10000), ("dense16384", 100, 800),
-                             ("dense16384-fp64", 50, 200)):
+        for name, st, wu in (("banded1e6-fp64", 100, 300), ("banded1e6-pp", 100, 300), ("laplacian64", 1000, 10000),
+                             ("dense16384", 100, 800), ("dense16384-fp64", 50, 200)):
             try:
                 sec[name] = secondary(name, st, wu, stream)
             except Exception as e:  # a secondary workload never hides the headline line
