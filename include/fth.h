@@ -305,8 +305,9 @@ typedef enum {
  * f(M).  The q-response of the scaled GLE is (gamma / alpha^2) g(M' / alpha^2)
  * (Sec. I), so first est *= alpha^2 / gamma and r' = r / alpha^2,
  * m' = m / alpha^2; then the target's identity above.  (Momentum-form
- * estimates, acc_pp, scale as gamma g_p(M' / alpha^2): with
- * alpha = 1 the two forms unscale alike, which is how they are passed here.)
+ * estimates, acc_pp, scale as gamma g_p(M' / alpha^2): multiply them by
+ * alpha^-2 before passing them here, as the server does for its
+ * momentum-form requests; with alpha = 1 the two forms unscale alike.)
  * kind_weight[k] is the
  * number of identity entries output k contains: 0 for an off-diagonal
  * element, 1 for a diagonal element, n for a trace over n rows (the ln shift
