@@ -188,7 +188,8 @@ def test_banded_1e6_full_size_blocked():
     """Banded SPD N = 1e6, R = 32, Fermi GLE, FP32, diagonal + 1024 pairs, in
     the benchmark's blocked launch shape (5 steps per launch, 1024-thread
     workgroups, 20-step graphs): the whole state and the accumulators against
-    the oracle after 5 and 100 steps."""
+    the oracle after 5 and 100 steps, and over steps 1000 to 1010 from the
+    GPU's own state at step 1000."""
     print("[fullsize] banded 1e6 R=32 blocked KT=5", flush=True)
     M = fi.banded_spd_csr(1_000_000, 3003)
     g = fi.load_gle("fermi_b20_ns4")
@@ -210,7 +211,38 @@ def test_banded_1e6_full_size_blocked():
     est, se, nsamp = sol.read()
     m_o, se_o = orc.estimates()
     assert normwise(est, m_o) <= 1e-3
+    # late steps: the oracle restarts from the GPU's state at step 1000 (noise counters and block
+    # bookkeeping from the global step index) and both take one pair of blocked launches
+    del orc
+    sol.run(900)
+    late = oracle.OracleRun(M64, g.A_p, g.C_p, h, 32, np.concatenate([pairs, fi.diag_pairs(M.n)]), seed=4,
+                            block_len=10)
+    late_step_check(sol, late, 1000, 10, 1e-4, "band1e6")
     sol.close()
+
+
+def late_step_check(sol, orc, at, more, tol, label):
+    """Continue sol (already at step `at`) and a fresh oracle started from
+    sol's state at that step by `more` steps; compare the state and what the
+    accumulators gained over those steps."""
+    q, p, s = sol.state()
+    blk0, s1_0, s2_0, nb0, step0 = sol.accumulators()
+    assert step0 == at
+    orc.step = at
+    orc.set_state(q, p, s)
+    sol.run(more)
+    orc.run(more)
+    q, p, s = sol.state()
+    blk, s1, s2, nb, step = sol.accumulators()
+    assert step == orc.step == at + more and nb - nb0 == int(orc.nblocks[0])
+    for name, a, b in (("q", q, orc.q), ("p", p, orc.p), ("s", s, orc.s),
+                       ("acc", (s1 - s1_0) + (blk - blk0), orc.s1 + orc.blk), ("s2", s2 - s2_0, orc.s2)):
+        if not np.any(b):
+            assert not np.any(a), name
+            continue
+        e = normwise(a, b)
+        print(f"  {label} late steps {at}..{at + more} {name}: {e:.2e}", flush=True)
+        assert e <= tol, (label, name, e)
 
 
 # ---------------------------------------------------------- invariances

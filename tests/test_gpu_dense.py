@@ -81,7 +81,8 @@ def test_dense_trajectory_parity(prec):
 def test_dense_full_size_two_steps():
     """N = 16384, R = 128, split-BF16x3 (the configuration the benchmark
     times): force against an FP64 GEMM on the full state, then two steps of
-    the whole path against the oracle."""
+    the whole path against the oracle, and two more from the GPU's own state
+    at step 1000."""
     n, R = 16384, 128
     print("[fullsize] dense 16384 generating matrix", flush=True)
     M = fi.dense_ggt(n, 4004)
@@ -103,6 +104,26 @@ def test_dense_full_size_two_steps():
     for name, a, b in (("q", qg, orc.q), ("p", pg, orc.p), ("s", sg, orc.s)):
         e = normwise(a, b)
         print(f"[fullsize] {name}: {e:.2e}", flush=True)
+        assert e <= 1e-4
+    # late steps: the oracle restarts from the GPU's state at step 1000 (noise counters and block
+    # bookkeeping from the global step index); both take two more steps
+    del orc
+    sol.run(998)
+    q0, p0, s0 = sol.state()
+    blk0, s1_0, s2_0, nb0, step0 = sol.accumulators()
+    assert step0 == 1000
+    late = oracle.OracleRun(M64, g.A_p, g.C_p, h, R, np.concatenate([pairs, fi.diag_pairs(n)]), seed=5)
+    late.step = 1000
+    late.set_state(q0, p0, s0)
+    sol.run(2)
+    late.run(2)
+    qg, pg, sg = sol.state()
+    blk, s1, s2, nb, step = sol.accumulators()
+    assert step == late.step == 1002
+    for name, a, b in (("q", qg, late.q), ("p", pg, late.p), ("s", sg, late.s),
+                       ("acc", (s1 - s1_0) + (blk - blk0), late.s1 + late.blk)):
+        e = normwise(a, b)
+        print(f"[fullsize] late steps 1000..1002 {name}: {e:.2e}", flush=True)
         assert e <= 1e-4
     sol.close()
 
