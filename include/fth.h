@@ -345,7 +345,8 @@ size_t fth_footprint_bytes(const fth_matrix* M, int32_t ns, int32_t replicas,
  *    HBM budget and fewer than max_active run;
  *  - work is issued in chunks, each on its own stream: a running request
  *    that is not packed advances alone on its context's stream; sparse FP32
- *    requests with the same ns are packed into one persistent kernel per step
+ *    requests of 4 to 256 replicas with the same ns are packed into one
+ *    persistent kernel per step
  *    (a device work list of row and pair tiles of all members, one captured
  *    hipGraph per chunk length) on the group's stream; dense and FP64
  *    requests run their own GEMM and step kernels.  Chunks of different
