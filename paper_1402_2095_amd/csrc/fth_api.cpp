@@ -338,15 +338,22 @@ fth_status upload_dense(fth_ctx* c, const std::vector<double>& M) {
     return FTH_OK;
 }
 
-// Small dense systems: M [n][n] in the state precision for the persistent kernel.
+// Small dense systems: M [n][n] in the state precision for the persistent kernel,
+// column-major, so that the threads of consecutive rows read consecutive words
+// (M is only symmetric to the validation tolerance, so the copy is a transpose).
 fth_status upload_small(fth_ctx* c, const std::vector<double>& M) {
     const size_t cnt = M.size();
+    const size_t n = size_t(c->n);
     if (c->prec == FTH_FP64) {
+        std::vector<double> mt(cnt);
+        for (size_t i = 0; i < n; ++i)
+            for (size_t j = 0; j < n; ++j) mt[j * n + i] = M[i * n + j];
         HIP_OK(c->dalloc(&c->d_msmall, cnt * sizeof(double)));
-        HIP_OK(hipMemcpy(c->d_msmall, M.data(), cnt * sizeof(double), hipMemcpyHostToDevice));
+        HIP_OK(hipMemcpy(c->d_msmall, mt.data(), cnt * sizeof(double), hipMemcpyHostToDevice));
     } else {
         std::vector<float> mf(cnt);
-        for (size_t k = 0; k < cnt; ++k) mf[k] = float(M[k]);
+        for (size_t i = 0; i < n; ++i)
+            for (size_t j = 0; j < n; ++j) mf[j * n + i] = float(M[i * n + j]);
         HIP_OK(c->dalloc(&c->d_msmall, cnt * sizeof(float)));
         HIP_OK(hipMemcpy(c->d_msmall, mf.data(), cnt * sizeof(float), hipMemcpyHostToDevice));
     }
@@ -364,7 +371,7 @@ std::vector<double> dense_to_double(const fth_matrix* M) {
 }
 
 constexpr int64_t kSmallMaxNR = 4096;       // n * R handled by one workgroup
-constexpr size_t kSmallMaxLds = 64 * 1024;  // LDS budget of the persistent kernel
+constexpr size_t kSmallMaxLds = 152 * 1024;  // LDS budget of the persistent kernel (160 KB per workgroup)
 
 fth_status ensure_state(fth_ctx* c, int32_t R) {
     if (c->R != 0) {
@@ -379,7 +386,8 @@ fth_status ensure_state(fth_ctx* c, int32_t R) {
         const int64_t threads = c->n * (R / std::min(R, 4));
         const size_t rb = c->real_bytes();
         const size_t lds_base = size_t(c->n_out()) * 8 + 2 * size_t(c->n) * R * rb *
-                                (c->opt.acc_pp && c->npairs > 0 ? 2 : 1);
+                                (c->opt.acc_pp && c->npairs > 0 ? 2 : 1) +
+                                2 * size_t(c->ns + 1) * size_t(c->ns + 1) * rb;  // + T and S
         const bool small = c->n * R <= kSmallMaxNR && R <= 64 && threads <= 1024 && lds_base <= kSmallMaxLds;
         fth_status st2;
         if (small) {

@@ -34,7 +34,8 @@ struct StepArgs {
     int64_t rows_pad;
     // dense split-BF16x3 only: q_{n+1} split into bf16 hi/lo, tiled [rows_pad/8][R][2][8]
     uint16_t* qt;
-    // small dense systems: M [N][N] row-major in state precision; kept in LDS if m_in_lds
+    // small dense systems: M column-major (element (i, j) at j * N + i) in state precision;
+    // kept in LDS if m_in_lds
     const Real* mdense;
     int32_t m_in_lds;
     // state: q ping-pong [rows][R]; (p, s) ping-pong as well (step n reads buffer

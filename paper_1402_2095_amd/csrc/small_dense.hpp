@@ -22,11 +22,63 @@
 namespace fth {
 namespace dev {
 
-template <typename Real, int NS, int RPT>
-__global__ __launch_bounds__(1024) void small_dense_kernel(const StepArgs<Real> a, const int K) {
+// sum_j M_ij q_j over the row, in column order, for the thread's replicas, with M
+// column-major (mrow[j * N] = M_ij: consecutive rows read consecutive words, which
+// keeps LDS reads free of bank conflicts and global reads coalesced); the operands
+// of 8 columns are loaded before their FMAs so that the loads overlap
+template <typename Real, int RPT>
+__device__ __forceinline__ void row_force(const Real* mrow, const Real* q, int64_t N, int64_t R, Real* acc) {
+    constexpr int B = 8;
+#pragma unroll
+    for (int m = 0; m < RPT; ++m) acc[m] = Real(0);
+    int64_t j = 0;
+    for (; j + B <= N; j += B) {
+        Real mb[B];
+        Vec<Real, RPT> qb[B];
+#pragma unroll
+        for (int u = 0; u < B; ++u) {
+            mb[u] = mrow[(j + u) * N];
+            qb[u] = load_vec<Real, RPT>(q + (j + u) * R);
+        }
+#pragma unroll
+        for (int u = 0; u < B; ++u)
+#pragma unroll
+            for (int m = 0; m < RPT; ++m) acc[m] = fmaR(mb[u], qb[u].v[m], acc[m]);
+    }
+    for (; j < N; ++j) {
+        const Real mij = mrow[j * N];
+        const Vec<Real, RPT> qj = load_vec<Real, RPT>(q + j * R);
+#pragma unroll
+        for (int m = 0; m < RPT; ++m) acc[m] = fmaR(mij, qj.v[m], acc[m]);
+    }
+}
+
+// sum_r x_r y_r in FP64 over the replicas, in replica order, 4 replicas loaded at a time
+template <typename Real>
+__device__ __forceinline__ double pair_dot(const Real* x, const Real* y, int64_t R) {
+    double acc = 0.0;
+    int64_t r = 0;
+    for (; r + 4 <= R; r += 4) {
+        Real u[4], v[4];
+#pragma unroll
+        for (int k = 0; k < 4; ++k) {
+            u[k] = x[r + k];
+            v[k] = y[r + k];
+        }
+#pragma unroll
+        for (int k = 0; k < 4; ++k) acc += double(u[k]) * double(v[k]);
+    }
+    for (; r < R; ++r) acc += double(x[r]) * double(y[r]);
+    return acc;
+}
+
+// MAXT is the largest workgroup the instantiation accepts: at 256 or 512 threads a
+// thread may hold 512 or 256 registers, so the state of wide thermostats (and the
+// FP64 form) stays in registers instead of spilling to scratch memory.
+template <typename Real, int NS, int RPT, int MAXT>
+__global__ __launch_bounds__(MAXT) void small_dense_kernel(const StepArgs<Real> a, const int K) {
     extern __shared__ double smem_d[];
     constexpr int D = NS + 1;
-    using V = Vec<Real, RPT>;
     const int64_t N = a.N, R = a.R;
     const int tid = threadIdx.x, nthr = blockDim.x;
     const int tpr = 1 << a.lg_tpr;
@@ -38,16 +90,17 @@ __global__ __launch_bounds__(1024) void small_dense_kernel(const StepArgs<Real> 
     const int64_t np = a.npairs, nacc = np + nd;  // per kind (q, then p)
     const bool pp_pairs = kp && np > 0;
     // LDS layout: block sums (FP64) [q pairs | q diag | p pairs | p diag] | q[2][N][R]
-    //             | p[2][N][R] (p-p pairs only) | M[N][N] (if in LDS)
+    //             | p[2][N][R] (p-p pairs only) | T, S [2][D][D] | M column-major (if in LDS)
     double* bl = smem_d;
     Real* qb = reinterpret_cast<Real*>(bl + (kp ? 2 : 1) * nacc);
     Real* pb = qb + 2 * N * R;
-    const Real* Mx = a.mdense;
-    if (a.m_in_lds) {
-        Real* Ml = pb + (pp_pairs ? 2 * N * R : 0);
+    Real* tsl = pb + (pp_pairs ? 2 * N * R : 0);  // T and S, read in every step
+    for (int x = tid; x < 2 * D * D; x += nthr) tsl[x] = a.TS[x];
+    // M in LDS when it fits; the force loop is written once per address space (a pointer that
+    // may be either would compile to flat loads, which wait on both the LDS and vector counters)
+    Real* Ml = tsl + 2 * D * D;
+    if (a.m_in_lds)
         for (int64_t x = tid; x < N * N; x += nthr) Ml[x] = a.mdense[x];
-        Mx = Ml;
-    }
     const int64_t n0 = a.step_base[0];
     const Real* qg = (n0 & 1) ? a.q1 : a.q0;
     for (int64_t x = tid; x < N * R; x += nthr) qb[(n0 & 1) * N * R + x] = qg[x];
@@ -68,8 +121,15 @@ __global__ __launch_bounds__(1024) void small_dense_kernel(const StepArgs<Real> 
         for (int c = 0; c < NS; ++c) st.s[c] = load_vec<Real, RPT>(psrow + (c + 1) * cs);
         if (pp_pairs) store_vec<Real, RPT>(pb + (n0 & 1) * N * R + i * R + r0, st.p);
     }
-    const Real* T = a.TS;
-    const Real* S = a.TS + D * D;
+    const Real* T = tsl;
+    const Real* S = tsl + D * D;
+    // a thread's first pair stays in registers (all of its pairs when there are no more
+    // pairs than threads)
+    int64_t ia0 = 0, ib0 = 0;
+    if (tid < np) {
+        ia0 = a.pairs[2 * tid];
+        ib0 = a.pairs[2 * tid + 1];
+    }
     bool ok = true;
     __syncthreads();
 
@@ -94,28 +154,26 @@ __global__ __launch_bounds__(1024) void small_dense_kernel(const StepArgs<Real> 
         };
         if (acc_on) {
             for (int64_t pk = tid; pk < np; pk += nthr) {
-                const int64_t ia = a.pairs[2 * pk], ib = a.pairs[2 * pk + 1];
-                double x = 0.0;
-                for (int64_t r = 0; r < R; ++r) x += double(qr[ia * R + r]) * double(qr[ib * R + r]);
+                int64_t ia = ia0, ib = ib0;
+                if (pk != tid) {
+                    ia = a.pairs[2 * pk];
+                    ib = a.pairs[2 * pk + 1];
+                }
+                const double x = pair_dot(qr + ia * R, qr + ib * R, R);
                 fold(bl, a.ps1, a.ps2, pk, pk, x);
                 if (pp_pairs) {
                     const Real* pr = pb + (n & 1) * N * R;
-                    double y = 0.0;
-                    for (int64_t r = 0; r < R; ++r) y += double(pr[ia * R + r]) * double(pr[ib * R + r]);
+                    const double y = pair_dot(pr + ia * R, pr + ib * R, R);
                     fold(bl, a.pp_s1, a.pp_s2, pk, nacc + pk, y);
                 }
             }
         }
         if (active) {
             Real acc[RPT];
-#pragma unroll
-            for (int m = 0; m < RPT; ++m) acc[m] = Real(0);
-            for (int64_t j = 0; j < N; ++j) {
-                const Real mij = Mx[i * N + j];
-                const V qj = load_vec<Real, RPT>(qr + j * R + r0);
-#pragma unroll
-                for (int m = 0; m < RPT; ++m) acc[m] = fmaR(mij, qj.v[m], acc[m]);
-            }
+            if (a.m_in_lds)
+                row_force<Real, RPT>(Ml + i, qr + r0, N, R, acc);
+            else
+                row_force<Real, RPT>(a.mdense + i, qr + r0, N, R, acc);
             if (nd) {
                 const double x = dot_row<Real, RPT>(st.q, st.q, tpr);
                 if (rq == 0 && acc_on) fold(bl, a.ds1, a.ds2, i, np + i, x);
@@ -165,43 +223,51 @@ __global__ __launch_bounds__(1024) void small_dense_kernel(const StepArgs<Real> 
     if (tid == 0) const_cast<int64_t*>(a.step_base)[0] = nend;
 }
 
-template <typename Real, int NS>
+template <typename Real, int NS, int MAXT>
 const void* pick_small_rpt(int rpt) {
     switch (rpt) {
-        case 1: return reinterpret_cast<const void*>(&small_dense_kernel<Real, NS, 1>);
-        case 2: return reinterpret_cast<const void*>(&small_dense_kernel<Real, NS, 2>);
-        case 4: return reinterpret_cast<const void*>(&small_dense_kernel<Real, NS, 4>);
+        case 1: return reinterpret_cast<const void*>(&small_dense_kernel<Real, NS, 1, MAXT>);
+        case 2: return reinterpret_cast<const void*>(&small_dense_kernel<Real, NS, 2, MAXT>);
+        case 4: return reinterpret_cast<const void*>(&small_dense_kernel<Real, NS, 4, MAXT>);
         default: return nullptr;
     }
 }
 
-template <typename Real>
-const void* pick_small(int ns, int rpt) {
+template <typename Real, int MAXT>
+const void* pick_small_ns(int ns, int rpt) {
     switch (ns) {
-        case 0: return pick_small_rpt<Real, 0>(rpt);
-        case 1: return pick_small_rpt<Real, 1>(rpt);
-        case 2: return pick_small_rpt<Real, 2>(rpt);
-        case 3: return pick_small_rpt<Real, 3>(rpt);
-        case 4: return pick_small_rpt<Real, 4>(rpt);
-        case 5: return pick_small_rpt<Real, 5>(rpt);
-        case 6: return pick_small_rpt<Real, 6>(rpt);
-        case 7: return pick_small_rpt<Real, 7>(rpt);
-        case 8: return pick_small_rpt<Real, 8>(rpt);
-        case 9: return pick_small_rpt<Real, 9>(rpt);
-        case 10: return pick_small_rpt<Real, 10>(rpt);
+        case 0: return pick_small_rpt<Real, 0, MAXT>(rpt);
+        case 1: return pick_small_rpt<Real, 1, MAXT>(rpt);
+        case 2: return pick_small_rpt<Real, 2, MAXT>(rpt);
+        case 3: return pick_small_rpt<Real, 3, MAXT>(rpt);
+        case 4: return pick_small_rpt<Real, 4, MAXT>(rpt);
+        case 5: return pick_small_rpt<Real, 5, MAXT>(rpt);
+        case 6: return pick_small_rpt<Real, 6, MAXT>(rpt);
+        case 7: return pick_small_rpt<Real, 7, MAXT>(rpt);
+        case 8: return pick_small_rpt<Real, 8, MAXT>(rpt);
+        case 9: return pick_small_rpt<Real, 9, MAXT>(rpt);
+        case 10: return pick_small_rpt<Real, 10, MAXT>(rpt);
         default: return nullptr;
     }
+}
+
+// the instantiation with the smallest workgroup bound that admits `block` threads
+template <typename Real>
+const void* pick_small(int ns, int rpt, int block) {
+    if (block <= 256) return pick_small_ns<Real, 256>(ns, rpt);
+    if (block <= 512) return pick_small_ns<Real, 512>(ns, rpt);
+    return pick_small_ns<Real, 1024>(ns, rpt);
 }
 
 }  // namespace dev
 
 template <typename Real>
 int launch_small_dense_impl(const StepArgs<Real>& a, const StepLaunch& L, int K, size_t lds_bytes, void* stream) {
-    const void* fn = dev::pick_small<Real>(L.ns, L.rpt);
-    if (fn == nullptr) return -2;
     const int64_t threads = a.N << a.lg_tpr;
     const int block = int((threads + 63) / 64 * 64);
     if (block > 1024) return -3;
+    const void* fn = dev::pick_small<Real>(L.ns, L.rpt, block);
+    if (fn == nullptr) return -2;
     StepArgs<Real> copy = a;
     int k = K;
     void* args[] = {&copy, &k};

@@ -1,11 +1,7 @@
-// Instantiations of the persistent small-system kernel.
+// FP64 instantiations of the persistent small-system kernel.
 #include "small_dense.hpp"
 
 namespace fth {
-template <>
-int launch_small_dense<float>(const StepArgs<float>& a, const StepLaunch& L, int K, size_t lds_bytes, void* stream) {
-    return launch_small_dense_impl<float>(a, L, K, lds_bytes, stream);
-}
 template <>
 int launch_small_dense<double>(const StepArgs<double>& a, const StepLaunch& L, int K, size_t lds_bytes,
                                void* stream) {
