@@ -385,7 +385,7 @@ fth_status ensure_state(fth_ctx* c, int32_t R) {
     if (c->dense() && !c->m_uploaded) {
         const int64_t threads = c->n * (R / std::min(R, 4));
         const size_t rb = c->real_bytes();
-        const size_t lds_base = size_t(c->n_out()) * 8 + 2 * size_t(c->n) * R * rb *
+        const size_t lds_base = (size_t(c->n_out()) + 3) * 8 + 2 * size_t(c->n) * R * rb *
                                 (c->opt.acc_pp && c->npairs > 0 ? 2 : 1) +
                                 2 * size_t(c->ns + 1) * size_t(c->ns + 1) * rb;  // + T and S
         const bool small = c->n * R <= kSmallMaxNR && R <= 64 && threads <= 1024 && lds_base <= kSmallMaxLds;

@@ -53,20 +53,18 @@ __device__ __forceinline__ void row_force(const Real* mrow, const Real* q, int64
     }
 }
 
-// sum_r x_r y_r in FP64 over the replicas, in replica order, 4 replicas loaded at a time
+// sum_r x_r y_r in FP64 over the replicas, in replica order; with R a multiple of 4
+// (always, from 4 replicas on) the rows are read 4 replicas per load
 template <typename Real>
 __device__ __forceinline__ double pair_dot(const Real* x, const Real* y, int64_t R) {
     double acc = 0.0;
     int64_t r = 0;
-    for (; r + 4 <= R; r += 4) {
-        Real u[4], v[4];
+    if ((R & 3) == 0) {
+        for (; r < R; r += 4) {
+            const Vec<Real, 4> u = load_vec<Real, 4>(x + r), v = load_vec<Real, 4>(y + r);
 #pragma unroll
-        for (int k = 0; k < 4; ++k) {
-            u[k] = x[r + k];
-            v[k] = y[r + k];
+            for (int m = 0; m < 4; ++m) acc += double(u.v[m]) * double(v.v[m]);
         }
-#pragma unroll
-        for (int k = 0; k < 4; ++k) acc += double(u[k]) * double(v[k]);
     }
     for (; r < R; ++r) acc += double(x[r]) * double(y[r]);
     return acc;
@@ -92,7 +90,8 @@ __global__ __launch_bounds__(MAXT) void small_dense_kernel(const StepArgs<Real> 
     // LDS layout: block sums (FP64) [q pairs | q diag | p pairs | p diag] | q[2][N][R]
     //             | p[2][N][R] (p-p pairs only) | T, S [2][D][D] | M column-major (if in LDS)
     double* bl = smem_d;
-    Real* qb = reinterpret_cast<Real*>(bl + (kp ? 2 : 1) * nacc);
+    // (state buffers start on a 32-byte boundary, the alignment of a 4-replica FP64 vector)
+    Real* qb = reinterpret_cast<Real*>(bl + (((kp ? 2 : 1) * nacc + 3) & ~int64_t(3)));
     Real* pb = qb + 2 * N * R;
     Real* tsl = pb + (pp_pairs ? 2 * N * R : 0);  // T and S, read in every step
     for (int x = tid; x < 2 * D * D; x += nthr) tsl[x] = a.TS[x];
