@@ -74,9 +74,11 @@ typedef enum { FTH_DENSE = 0, FTH_CSR = 1 } fth_format;
 /* State precision / force form. */
 typedef enum {
     FTH_FP64 = 0,            /* FP64 state, FP64 force (plain FP64 form) */
-    FTH_FP32 = 1,            /* FP32 state, FP32 force (CSR) */
+    FTH_FP32 = 1,            /* FP32 state, FP32 force (CSR; dense systems of one
+                                workgroup, or with opt.replicas <= 8) */
     FTH_FP32_BF16X3 = 2      /* FP32 state, dense force as split-BF16x3 on MFMA
-                                with FP32 accumulation (dense only) */
+                                with FP32 accumulation (dense only; with at most 8
+                                replicas the force is FP32 matrix-vector products) */
 } fth_precision;
 
 /* The matrix M (Sec. I: the Hessian of the harmonic potential).
@@ -188,8 +190,11 @@ fth_status fth_create(const fth_matrix* M, const fth_gle* gle, double dt,
  * replicas (cumulative: continues from the previous call).  The first call
  * fixes R (replicas == 0 uses opt.replicas); a later call with another
  * non-zero R returns FTH_ESTATE.  R must be a power of two <= 512 for the
- * sparse kernels.  The first call also runs the autotuner when opt.tune is
- * set, so nsteps == 0 fixes R and the launch shape without advancing.
+ * sparse kernels; dense systems beyond one workgroup (N R > 4096) take R in
+ * {16, 32, 64, 128} on the matrix cores or R in {1, 2, 4, 8} as
+ * matrix-vector products (FTH_EUNSUPPORTED otherwise).  The first call also
+ * runs the autotuner when opt.tune is set, so nsteps == 0 fixes R and the
+ * launch shape without advancing.
  * Returns FTH_ENONFINITE (and poisons the context) if any state value
  * became non-finite; FTH_ESTATE on a poisoned context. */
 fth_status fth_run(fth_ctx* ctx, int64_t nsteps, int32_t replicas);
@@ -231,9 +236,10 @@ fth_status fth_set_state(fth_ctx* ctx, const double* q, const double* p, const d
 
 /* Force check for dense contexts: F = -M q for a host state q[n*R] (index
  * i*R + r, values rounded to the state precision), computed with the same
- * device GEMM and partial-sum order as a time step, on scratch buffers (the
- * trajectory is not touched); F[n*R] receives the result as double.
- * FTH_ESTATE before R is fixed; FTH_EUNSUPPORTED for CSR contexts. */
+ * device kernels and partial-sum order as a time step, on scratch buffers
+ * (the trajectory is not touched); F[n*R] receives the result as double.
+ * FTH_ESTATE before R is fixed; FTH_EUNSUPPORTED for CSR contexts and
+ * dense systems of one workgroup. */
 fth_status fth_force(fth_ctx* ctx, const double* q, double* F);
 
 /* For callers that cannot allocate device memory (code under HIP graph
@@ -252,8 +258,8 @@ fth_status fth_force(fth_ctx* ctx, const double* q, double* F);
  * Errors: FTH_EINVAL (NULL pointers, or a system whose work space exceeds
  * the 64 MiB array: 4 (1 + ksplit) P R bytes in the split form, 8 (1 +
  * ksplit) P R in FP64, P = n rounded up to the padded size), FTH_ESTATE
- * before R is fixed, FTH_EUNSUPPORTED for CSR or one-workgroup dense
- * contexts, FTH_EDEVICE on a launch failure. */
+ * before R is fixed, FTH_EUNSUPPORTED for CSR, one-workgroup dense and
+ * matrix-vector (R <= 8) dense contexts, FTH_EDEVICE on a launch failure. */
 fth_status fth_force_noalloc(fth_ctx* ctx, const void* q, void* F, void* hip_stream);
 
 /* GPU time in milliseconds of the most recent fth_run, measured with HIP

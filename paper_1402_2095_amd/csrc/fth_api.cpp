@@ -320,7 +320,8 @@ fth_status upload_dense(fth_ctx* c, const std::vector<double>& M) {
         return FTH_OK;
     }
     if (c->prec != FTH_FP32_BF16X3)
-        return fail(FTH_EUNSUPPORTED, "dense systems beyond one workgroup use FTH_FP32_BF16X3 or FTH_FP64");
+        return fail(FTH_EUNSUPPORTED,
+                    "dense systems beyond one workgroup use FTH_FP32_BF16X3 or FTH_FP64 (FTH_FP32 needs replicas <= 8)");
     ctx_scratch scratch(c);
     float* tmp = static_cast<float*>(scratch.get(cnt * sizeof(float)));
     if (!tmp) return fail(FTH_ENOMEM, "scratch allocation for the bf16 split failed");
@@ -356,6 +357,30 @@ fth_status upload_small(fth_ctx* c, const std::vector<double>& M) {
             for (size_t j = 0; j < n; ++j) mf[j * n + i] = float(M[i * n + j]);
         HIP_OK(c->dalloc(&c->d_msmall, cnt * sizeof(float)));
         HIP_OK(hipMemcpy(c->d_msmall, mf.data(), cnt * sizeof(float), hipMemcpyHostToDevice));
+    }
+    return FTH_OK;
+}
+
+// Dense M for the few-replica force (R < 16): row-major in the state precision
+// (FP32 for both FP32 forms), ld = n rounded up to 4, zero columns past n.
+fth_status upload_gemv(fth_ctx* c, const std::vector<double>& M) {
+    const int64_t n = c->n, ld = (n + 3) / 4 * 4;
+    c->rows_pad = ld;
+    c->ksplit = 1;
+    c->gemv = true;
+    const size_t cnt = size_t(n) * size_t(ld);
+    if (c->prec == FTH_FP64) {
+        std::vector<double> m(cnt, 0.0);
+        for (int64_t i = 0; i < n; ++i)
+            for (int64_t j = 0; j < n; ++j) m[size_t(i * ld + j)] = M[size_t(i * n + j)];
+        HIP_OK(c->dalloc(&c->d_m_hi, cnt * sizeof(double)));
+        HIP_OK(hipMemcpy(c->d_m_hi, m.data(), cnt * sizeof(double), hipMemcpyHostToDevice));
+    } else {
+        std::vector<float> m(cnt, 0.0f);
+        for (int64_t i = 0; i < n; ++i)
+            for (int64_t j = 0; j < n; ++j) m[size_t(i * ld + j)] = float(M[size_t(i * n + j)]);
+        HIP_OK(c->dalloc(&c->d_m_hi, cnt * sizeof(float)));
+        HIP_OK(hipMemcpy(c->d_m_hi, m.data(), cnt * sizeof(float), hipMemcpyHostToDevice));
     }
     return FTH_OK;
 }
@@ -396,17 +421,23 @@ fth_status ensure_state(fth_ctx* c, int32_t R) {
             c->small_m_in_lds = lds_base + size_t(c->n) * size_t(c->n) * rb <= kSmallMaxLds;
             c->small_lds = lds_base + (c->small_m_in_lds ? size_t(c->n) * size_t(c->n) * rb : 0);
             st2 = upload_small(c, c->m_host);
+        } else if (R == 1 || R == 2 || R == 4 || R == 8) {
+            st2 = upload_gemv(c, c->m_host);
         } else {
             if (R != 16 && R != 32 && R != 64 && R != 128)
-                return fail(FTH_EUNSUPPORTED, "dense systems of this size need R in {16, 32, 64, 128} (got %d)", R);
+                return fail(FTH_EUNSUPPORTED, "dense systems of this size need R in {1, 2, 4, 8, 16, 32, 64, 128} (got %d)",
+                            R);
             st2 = upload_dense(c, c->m_host);
         }
         if (st2 != FTH_OK) return st2;
         c->m_host.clear();
         c->m_host.shrink_to_fit();
         c->m_uploaded = true;
-    } else if (c->mfma() && R != 16 && R != 32 && R != 64 && R != 128) {
-        return fail(FTH_EUNSUPPORTED, "dense systems of this size need R in {16, 32, 64, 128} (got %d)", R);
+    } else if (c->mfma()) {
+        const bool few = R == 1 || R == 2 || R == 4 || R == 8;
+        if (c->gemv ? !few : (R != 16 && R != 32 && R != 64 && R != 128))
+            return fail(FTH_EUNSUPPORTED, "this dense context was set up for R in %s (got %d)",
+                        c->gemv ? "{1, 2, 4, 8}" : "{16, 32, 64, 128}", R);
     }
     c->R = R;
     c->rpt = rpt;
@@ -430,7 +461,7 @@ fth_status ensure_state(fth_ctx* c, int32_t R) {
         const size_t pb = size_t(c->ksplit) * size_t(c->rows_pad) * size_t(R) * rb;
         HIP_OK(c->dalloc(&c->d_part, pb));
         HIP_OK(hipMemsetAsync(c->d_part, 0, pb, c->stream));
-        if (c->prec == FTH_FP32_BF16X3) {
+        if (c->prec == FTH_FP32_BF16X3 && !c->gemv) {
             const size_t qtb = size_t(c->rows_pad) * size_t(R) * 2 * sizeof(uint16_t);
             HIP_OK(c->dalloc(reinterpret_cast<void**>(&c->d_qt), qtb));
             HIP_OK(hipMemsetAsync(c->d_qt, 0, qtb, c->stream));
@@ -539,13 +570,23 @@ fth::DenseGemmArgs gemm_args(fth_ctx* c, int k) {
     return g;
 }
 
+// The dense force partials of one step: the matrix-core GEMM, or for R < 16
+// the matrix-vector form.
+int launch_force(const fth_ctx* c, const fth::DenseGemmArgs& g) {
+    if (c->gemv)
+        return c->prec == FTH_FP64
+                   ? fth::launch_dense_gemv<double>(g, static_cast<const double*>(c->d_m_hi), c->n, c->rows_pad, c->stream)
+                   : fth::launch_dense_gemv<float>(g, static_cast<const float*>(c->d_m_hi), c->n, c->rows_pad, c->stream);
+    return c->prec == FTH_FP64 ? fth::launch_gemm_f64(g, c->stream) : fth::launch_gemm_bf16x3(g, c->stream);
+}
+
 // Enqueue one step with in-chunk offset k (global step = *d_step + k).
 fth_status enqueue_step(fth_ctx* c, int k) {
     int rc;
     if (c->dense()) {
         const fth::DenseGemmArgs g = gemm_args(c, k);
-        rc = c->prec == FTH_FP64 ? fth::launch_gemm_f64(g, c->stream) : fth::launch_gemm_bf16x3(g, c->stream);
-        if (rc != 0) return fail(FTH_EDEVICE, "dense GEMM launch failed (%d)", rc);
+        rc = launch_force(c, g);
+        if (rc != 0) return fail(FTH_EDEVICE, "dense force launch failed (%d)", rc);
         if (c->prec == FTH_FP64)
             rc = fth::launch_dense_epilogue<double>(step_args<double>(c), step_launch(c), k, c->stream);
         else
@@ -999,6 +1040,11 @@ size_t fth_footprint_bytes(const fth_matrix* M, int32_t ns, int32_t R, int64_t n
     if (M->format == FTH_CSR) {
         bytes += (n + 1) * 8 + size_t(M->nnz) * (4 + rb);
         bytes += n * size_t(R) * rb * 2 + 2 * ps_rows * size_t(R) * rb * size_t(1 + ns);
+    } else if ((R == 1 || R == 2 || R == 4 || R == 8) && int64_t(n) * R > kSmallMaxNR) {
+        const size_t ld = (n + 3) / 4 * 4;                                    // matrix-vector form
+        bytes += n * ld * rb;                                                  // M
+        bytes += 2 * ld * size_t(R) * rb + 2 * ps_rows * size_t(R) * rb * size_t(1 + ns);
+        bytes += ld * size_t(R) * rb;                                          // force partials
     } else {
         const size_t P = size_t(dense_rows_pad(int64_t(n)));
         const size_t ks = size_t(dense_ksplit(int64_t(P), precision));
@@ -1063,8 +1109,10 @@ fth_status fth_create(const fth_matrix* M_in, const fth_gle* gle_in, double dt, 
     if (st != FTH_OK) return st;
     if (M->format == FTH_CSR && opt.precision == FTH_FP32_BF16X3)
         return fail(FTH_EUNSUPPORTED, "split-BF16x3 applies to dense matrices only");
-    if (M->format == FTH_DENSE && opt.precision == FTH_FP32 && M->n > kSmallMaxNR)
-        return fail(FTH_EUNSUPPORTED, "dense systems beyond one workgroup use FTH_FP32_BF16X3 or FTH_FP64");
+    if (M->format == FTH_DENSE && opt.precision == FTH_FP32 && M->n > kSmallMaxNR &&
+        !(opt.replicas == 1 || opt.replicas == 2 || opt.replicas == 4 || opt.replicas == 8))
+        return fail(FTH_EUNSUPPORTED,
+                    "dense systems beyond one workgroup use FTH_FP32_BF16X3 or FTH_FP64 (FTH_FP32 needs replicas <= 8)");
     if (gle && (gle->ns > fth::kNsMax)) return fail(FTH_EUNSUPPORTED, "ns > %d not instantiated", fth::kNsMax);
 
     std::unique_ptr<fth_ctx> c(new fth_ctx());
@@ -1107,8 +1155,10 @@ fth_status fth_create(const fth_matrix* M_in, const fth_gle* gle_in, double dt, 
     // matrix
     if (c->dense()) {
         c->m_host = dense_to_double(M);
-        if (M->n > kSmallMaxNR) {  // cannot take the single-workgroup path for any R
-            st = upload_dense(c.get(), c->m_host);
+        if (M->n > kSmallMaxNR && opt.replicas != 0) {  // no single-workgroup path for any R
+            const int32_t R0 = opt.replicas;
+            st = (R0 == 1 || R0 == 2 || R0 == 4 || R0 == 8) ? upload_gemv(c.get(), c->m_host)
+                                                             : upload_dense(c.get(), c->m_host);
             if (st != FTH_OK) return st;
             c->m_host.clear();
             c->m_host.shrink_to_fit();
@@ -1339,8 +1389,9 @@ fth_status fth_force(fth_ctx* c, const double* q, double* F) {
     void* dq = alloc(size_t(P * R) * rb);
     void* dpart = alloc(size_t(c->ksplit) * size_t(P * R) * rb);
     int64_t* dstep = static_cast<int64_t*>(alloc(sizeof(int64_t)));
-    uint16_t* dqt = c->prec == FTH_FP32_BF16X3 ? static_cast<uint16_t*>(alloc(size_t(P * R) * 4)) : nullptr;
-    if (!dq || !dpart || !dstep || (c->prec == FTH_FP32_BF16X3 && !dqt)) return fail(FTH_ENOMEM, "scratch allocation failed");
+    const bool split = c->prec == FTH_FP32_BF16X3 && !c->gemv;
+    uint16_t* dqt = split ? static_cast<uint16_t*>(alloc(size_t(P * R) * 4)) : nullptr;
+    if (!dq || !dpart || !dstep || (split && !dqt)) return fail(FTH_ENOMEM, "scratch allocation failed");
     HIP_OK(hipMemset(dq, 0, size_t(P * R) * rb));
     HIP_OK(hipMemset(dstep, 0, sizeof(int64_t)));
     if (c->prec == FTH_FP64) {
@@ -1349,9 +1400,11 @@ fth_status fth_force(fth_ctx* c, const double* q, double* F) {
         std::vector<float> t(size_t(n * R));
         for (size_t k = 0; k < t.size(); ++k) t[k] = float(q[k]);
         HIP_OK(hipMemcpy(dq, t.data(), sizeof(float) * t.size(), hipMemcpyHostToDevice));
-        HIP_OK(hipMemset(dqt, 0, size_t(P * R) * 4));
-        if (fth::launch_qt_from_q(static_cast<const float*>(dq), dqt, n, P, int32_t(R), c->stream) != 0)
-            return fail(FTH_EDEVICE, "q split launch failed");
+        if (split) {
+            HIP_OK(hipMemset(dqt, 0, size_t(P * R) * 4));
+            if (fth::launch_qt_from_q(static_cast<const float*>(dq), dqt, n, P, int32_t(R), c->stream) != 0)
+                return fail(FTH_EDEVICE, "q split launch failed");
+        }
     }
     fth::DenseGemmArgs g = gemm_args(c, 0);
     g.qt = dqt;
@@ -1359,8 +1412,8 @@ fth_status fth_force(fth_ctx* c, const double* q, double* F) {
     g.q1 = dq;
     g.step_base = dstep;
     g.part = dpart;
-    const int rc = c->prec == FTH_FP64 ? fth::launch_gemm_f64(g, c->stream) : fth::launch_gemm_bf16x3(g, c->stream);
-    if (rc != 0) return fail(FTH_EDEVICE, "dense GEMM launch failed (%d)", rc);
+    const int rc = launch_force(c, g);
+    if (rc != 0) return fail(FTH_EDEVICE, "dense force launch failed (%d)", rc);
     HIP_OK(hipStreamSynchronize(c->stream));
     const size_t pc = size_t(c->ksplit) * size_t(P * R);
     if (c->prec == FTH_FP64) {
@@ -1394,6 +1447,10 @@ fth_status fth_kernel_name(const fth_ctx* c, char* name, size_t len) {
     if (c->small)
         std::snprintf(name, len, "small_dense_kernel<%s,NS=%d,RPT=%d> (persistent, M in %s)",
                       c->prec == FTH_FP64 ? "double" : "float", c->ns, c->rpt, c->small_m_in_lds ? "LDS" : "global");
+    else if (c->gemv)
+        std::snprintf(name, len, "dense_gemv_kernel<%s,R=%d> + dense_epilogue_kernel<%s,NS=%d,RPT=%d,NT=%d>",
+                      c->prec == FTH_FP64 ? "double" : "float", c->R, c->prec == FTH_FP64 ? "double" : "float", c->ns,
+                      c->rpt, int(c->nt));
     else if (c->dense())
         std::snprintf(name, len, "%s<RT=%d,ksplit=%d> + dense_epilogue_kernel<%s,NS=%d,RPT=%d,NT=%d>",
                       c->prec == FTH_FP64 ? "gemm_f64_kernel" : "gemm_bf16x3_kernel", c->R / 16, c->ksplit,

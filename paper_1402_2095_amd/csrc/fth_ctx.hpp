@@ -38,6 +38,7 @@ struct fth_ctx {
     bool qt_dirty = true;
     // small dense systems: persistent single-workgroup kernel, M [n][n] in state precision
     bool small = false;
+    bool gemv = false;  // dense, R < 16: the force as R matrix-vector products (dense_gemv.hip)
     void* d_msmall = nullptr;
     size_t small_lds = 0;
     int small_m_in_lds = 0;

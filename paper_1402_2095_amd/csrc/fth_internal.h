@@ -201,6 +201,10 @@ template <typename Real>
 int launch_dense_epilogue(const StepArgs<Real>& a, const StepLaunch& L, int k, void* stream);
 int launch_gemm_bf16x3(const DenseGemmArgs& g, void* stream);
 int launch_gemm_f64(const DenseGemmArgs& g, void* stream);
+// Dense force for R in {1, 2, 4, 8}: part[i][r] = (M q_n)_ir with M row-major [N][ld]
+// (ld a multiple of 4, >= N, <= g.rows_pad) in the state precision.
+template <typename Real>
+int launch_dense_gemv(const DenseGemmArgs& g, const Real* M, int64_t N, int64_t ld, void* stream);
 // M [P][P] FP32 -> bf16 hi/lo parts in the split GEMM's tiled layout (4 P^2 bytes at mt).
 int launch_split_bf16_tiled(const float* m, void* mt, int64_t P, void* stream);
 int launch_qt_from_q(const float* q, uint16_t* qt, int64_t N, int64_t rows_pad, int32_t R, void* stream);

@@ -83,7 +83,8 @@ using namespace fth::host;
 
 extern "C" fth_status fth_force_noalloc(fth_ctx* c, const void* q, void* F, void* hip_stream) {
     if (!c || !q || !F) return fail(FTH_EINVAL, "invalid arguments");
-    if (!c->mfma()) return fail(FTH_EUNSUPPORTED, "fth_force_noalloc is provided for dense contexts on the matrix-core path");
+    if (!c->mfma() || c->gemv)
+        return fail(FTH_EUNSUPPORTED, "fth_force_noalloc is provided for dense contexts on the matrix-core path");
     if (c->R == 0) return fail(FTH_ESTATE, "replica count not fixed");
     const int64_t P = c->rows_pad, R = c->R, n = c->n;
     const bool f64 = c->prec == FTH_FP64;

@@ -78,6 +78,50 @@ def test_dense_trajectory_parity(prec):
     sol.close()
 
 
+@pytest.mark.parametrize("n,R,prec,steps", [(4200, 1, fth.FTH_FP64, (1, 10, 100, 1000)),
+                                             (4200, 2, fth.FTH_FP32_BF16X3, (1, 10, 100, 1000)),
+                                             (2100, 4, fth.FTH_FP32, (1, 10, 100, 1000)),
+                                             (1100, 8, fth.FTH_FP64, (1, 10, 100, 1000)),
+                                             (5003, 8, fth.FTH_FP32_BF16X3, (1, 10, 100))],
+                         ids=["4200-R1-fp64", "4200-R2-split", "2100-R4-fp32", "1100-R8-fp64", "5003-R8-split"])
+def test_few_replica_dense_against_oracle(n, R, prec, steps):
+    """Dense systems beyond one workgroup with R <= 8 (the paper's own runs
+    use a single trajectory): the force as R matrix-vector products in the
+    state precision, against an FP64 GEMV, and the trajectory and
+    accumulators against the oracle."""
+    print(f"[few-replica dense] n={n} R={R} prec={prec}", flush=True)
+    M, h = dense_case(n, 91)
+    M64 = M.astype(np.float64)
+    g = fi.load_gle("invsqrt_ns4")
+    pairs = fi.random_pairs(n, 32, 8)
+    sol = fth.Solver(M, g.A_p, g.C_p, h, pairs=pairs, replicas=R, precision=prec, seed=3, stream_id=2, burn_in=3,
+                     block_len=9, acc_diag=True, steps_per_graph=16)
+    rng = np.random.default_rng(n + R)
+    q = rng.normal(size=(n, R))
+    if prec != fth.FTH_FP64:
+        q = q.astype(np.float32).astype(np.float64)
+    err = normwise(sol.force(q), -(M64 @ q))
+    print(f"  force normwise error {err:.2e} ({sol.kernel_name})", flush=True)
+    assert "dense_gemv_kernel" in sol.kernel_name
+    assert err <= (1e-13 if prec == fth.FTH_FP64 else 2e-5)
+    orc = oracle.OracleRun(M64, g.A_p, g.C_p, h, R, np.concatenate([pairs, fi.diag_pairs(n)]), seed=3, stream=2,
+                           burn_in=3, block_len=9)
+    tol = 1e-10 if prec == fth.FTH_FP64 else 1e-4
+    done = 0
+    for target in steps:
+        sol.run(target - done)
+        orc.run(target - done)
+        done = target
+        q, p, s = sol.state()
+        blk, s1, s2, nb, step = sol.accumulators()
+        errs = {"q": normwise(q, orc.q), "p": normwise(p, orc.p), "s": normwise(s, orc.s),
+                "acc": normwise(s1 + blk, orc.s1 + orc.blk)}
+        print(f"  step {done}: " + " ".join(f"{k}={v:.2e}" for k, v in errs.items()), flush=True)
+        for k, v in errs.items():
+            assert v <= tol, (n, R, prec, done, k, v)
+    sol.close()
+
+
 def test_dense_full_size_two_steps():
     """N = 16384, R = 128, split-BF16x3 (the configuration the benchmark
     times): force against an FP64 GEMM on the full state, then two steps of
@@ -166,8 +210,10 @@ def test_dense_path_selection_and_unsupported_shapes():
     small = fth.Solver(M, g.A_p, g.C_p, h, replicas=8, precision=fth.FTH_FP32_BF16X3).run(1)
     assert "small_dense_kernel" in small.kernel_name     # N R <= 4096: one persistent workgroup
     M, h = dense_case(4200, 1)
+    few = fth.Solver(M, g.A_p, g.C_p, h, replicas=8, precision=fth.FTH_FP32_BF16X3).run(1)
+    assert "dense_gemv_kernel" in few.kernel_name        # R <= 8: matrix-vector products
     with pytest.raises(fth.FthError) as e:
-        fth.Solver(M, g.A_p, g.C_p, h, replicas=8, precision=fth.FTH_FP32_BF16X3).run(1)
+        fth.Solver(M, g.A_p, g.C_p, h, replicas=256, precision=fth.FTH_FP32_BF16X3).run(1)
     assert e.value.status == fth.FTH_EUNSUPPORTED         # matrix-core path needs R in {16..128}
     with pytest.raises(fth.FthError) as e:
         fth.Solver(M, g.A_p, g.C_p, h, replicas=16, precision=fth.FTH_FP32)
