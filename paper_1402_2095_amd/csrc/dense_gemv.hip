@@ -6,10 +6,12 @@
 //
 // Layouts: M row-major Real [N][ld], ld = N rounded up to 4 with zero columns;
 // q_n [ld][R] (the context's q buffers, zero rows past N).  Wave w of workgroup
-// b owns rows ROWS (4 b + w) + (0 .. ROWS-1).  Lane l walks the columns
-// 4 l + 256 m, loading 4 entries of each of its rows and the 4 matching rows of
-// q_n per pass, and keeps one partial sum per (row, replica); the wave then adds
-// the 64 lanes' partials in a fixed butterfly, so the result does not depend on
+// b owns rows ROWS (4 b + w) + (0 .. ROWS-1).  The four waves walk the columns
+// together, 256 per pass: the pass's 256 rows of q_n are staged once in LDS for
+// all four (read from L2 by every wave, they cost more than M itself at R = 8),
+// lane l takes columns 4 l .. 4 l + 3 of the pass, loads 4 entries of each of its
+// rows, and keeps one partial sum per (row, replica); the wave then adds the 64
+// lanes' partials in a fixed butterfly, so the result does not depend on
 // scheduling.  The sums are written as the single K slice the dense epilogue
 // reads (part [1][ld][R]).
 #include "dense.hpp"
@@ -22,9 +24,12 @@ __global__ __launch_bounds__(256) void dense_gemv_kernel(const DenseGemmArgs g, 
                                                          int64_t ld) {
     constexpr int ROWS = (sizeof(Real) == 8 && R == 8) ? 4 : 8;
     constexpr int VW = 4;
-    const int lane = threadIdx.x & 63;
-    const int64_t row0 = (int64_t(blockIdx.x) * 4 + (threadIdx.x >> 6)) * ROWS;
-    if (row0 >= N) return;  // the whole wave; no barrier follows
+    constexpr int CH = 64 * VW;          // columns per pass
+    constexpr int QV = CH / 4 * R;       // 4-value vectors of q_n per pass
+    __shared__ Vec<Real, 4> qs[2][QV];   // the pass's rows of q_n, double-buffered
+    const int tid = threadIdx.x, lane = tid & 63;
+    const int64_t row0 = (int64_t(blockIdx.x) * 4 + (tid >> 6)) * ROWS;
+    const bool live = row0 < N;  // a wave past the last row still loads q_n and meets the barriers
     const int64_t n = g.step_base[0] + g.k;
     const Real* __restrict__ q = static_cast<const Real*>((n & 1) ? g.q1 : g.q0);
     Real* part = static_cast<Real*>(g.part);
@@ -37,24 +42,36 @@ __global__ __launch_bounds__(256) void dense_gemv_kernel(const DenseGemmArgs g, 
     for (int rr = 0; rr < ROWS; ++rr)
 #pragma unroll
         for (int r = 0; r < R; ++r) acc[rr][r] = Real(0);
-    for (int64_t j = int64_t(lane) * VW; j < ld; j += 64 * VW) {
-        // q_n rows j .. j+3: 4 R consecutive values
-        Vec<Real, 4> qv[R];
+    // vector x of a pass starting at column j0 holds q_n elements [4x, 4x + 4) of rows
+    // j0 .. j0 + CH - 1, i.e. from row j0 + 4x / R on (ld is a multiple of 4)
+    auto stage = [&](int buf, int64_t j0) {
+        for (int x = tid; x < QV; x += 256)
+            if (j0 + 4 * x / R < ld) qs[buf][x] = load_vec<Real, 4>(q + j0 * R + 4 * x);
+    };
+    const int64_t npass = (ld + CH - 1) / CH;
+    stage(0, 0);
+    __syncthreads();
+    for (int64_t p = 0; p < npass; ++p) {
+        const int64_t j0 = p * CH, j = j0 + int64_t(lane) * VW;
+        if (p + 1 < npass) stage(int((p + 1) & 1), j0 + CH);  // last read before the previous barrier
+        if (live && j < ld) {
+            const Vec<Real, 4>* qv = &qs[p & 1][lane * R];
+            Vec<Real, 4> mv[ROWS];
 #pragma unroll
-        for (int u = 0; u < R; ++u) qv[u] = load_vec<Real, 4>(q + j * R + 4 * u);
-        Vec<Real, 4> mv[ROWS];
+            for (int rr = 0; rr < ROWS; ++rr) mv[rr] = load_vec<Real, 4>(mrow[rr] + j);
 #pragma unroll
-        for (int rr = 0; rr < ROWS; ++rr) mv[rr] = load_vec<Real, 4>(mrow[rr] + j);
+            for (int rr = 0; rr < ROWS; ++rr)
 #pragma unroll
-        for (int rr = 0; rr < ROWS; ++rr)
+                for (int c = 0; c < VW; ++c)
 #pragma unroll
-            for (int c = 0; c < VW; ++c)
-#pragma unroll
-                for (int r = 0; r < R; ++r) {
-                    const int e = c * R + r;  // element (j + c, r) of the 4 R loaded
-                    acc[rr][r] = fmaR(mv[rr].v[c], qv[e >> 2].v[e & 3], acc[rr][r]);
-                }
+                    for (int r = 0; r < R; ++r) {
+                        const int e = c * R + r;  // element (j + c, r) of the lane's 4 R values
+                        acc[rr][r] = fmaR(mv[rr].v[c], qv[e >> 2].v[e & 3], acc[rr][r]);
+                    }
+        }
+        __syncthreads();
     }
+    if (!live) return;
 #pragma unroll
     for (int rr = 0; rr < ROWS; ++rr)
 #pragma unroll
