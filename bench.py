@@ -310,7 +310,12 @@ def roofline(w: dict, r: dict, steps: int) -> dict:
                         "peak_tflops": peak, "issued_frac": issued / per_unit_s / 1e12 / peak,
                         "busy_frac_counter": cnt.get("mfma_busy")}
         if w["prec"] == fth.FTH_FP64:
+            # 2 N^2 R flops at the FP64 matrix-core peak take longer than M's bytes at 8 TB/s: the
+            # roofline is the MFMA one, with the byte figure kept beside it
             roof["bound_by"] = "FP64 MFMA (2 N^2 R flops at 78.6 TFLOP/s exceed M's bytes at 8 TB/s)"
+            roof["hbm"] = {"achieved": roof["achieved"], "peak": HBM_PEAK_GBS, "unit": "GB/s", "frac": roof["frac"]}
+            tf = flops / per_unit_s / 1e12
+            roof.update(bound="mfma", achieved=tf, peak=peak, unit="TFLOP/s", frac=tf / peak)
     return roof
 
 
@@ -324,8 +329,9 @@ def secondary(name: str, steps: int, warmup: int, stream) -> dict:
            "dtype": "f64" if w["prec"] == fth.FTH_FP64 else "f32", "kernel": r["kernel"],
            "ms_per_step": r["wall"] * 1e3 / steps, "value": w["n"] * w["R"] * steps / r["wall"],
            "steps": steps, "warmup": warmup,
-           "roofline": {k: roof[k] for k in ("bound", "achieved", "frac", "avg_unit_us", "traffic") if k in roof}}
-    for k in ("cache_resident", "mfma", "bound_by"):
+           "roofline": {k: roof[k] for k in ("bound", "achieved", "peak", "unit", "frac", "avg_unit_us", "traffic")
+                        if k in roof}}
+    for k in ("cache_resident", "mfma", "bound_by", "hbm"):
         if k in roof:
             out["roofline"][k] = roof[k]
     log(f"secondary {name}: {out['ms_per_step'] * 1e3:.1f} us/step")
