@@ -81,9 +81,11 @@ def test_dense_trajectory_parity(prec):
 @pytest.mark.parametrize("n,R,prec,steps", [(4200, 1, fth.FTH_FP64, (1, 10, 100, 1000)),
                                              (4200, 2, fth.FTH_FP32_BF16X3, (1, 10, 100, 1000)),
                                              (2100, 4, fth.FTH_FP32, (1, 10, 100, 1000)),
+                                             (4500, 1, fth.FTH_FP32, (1, 10, 100, 1000)),
                                              (1100, 8, fth.FTH_FP64, (1, 10, 100, 1000)),
                                              (5003, 8, fth.FTH_FP32_BF16X3, (1, 10, 100))],
-                         ids=["4200-R1-fp64", "4200-R2-split", "2100-R4-fp32", "1100-R8-fp64", "5003-R8-split"])
+                         ids=["4200-R1-fp64", "4200-R2-split", "2100-R4-fp32", "4500-R1-fp32", "1100-R8-fp64",
+                              "5003-R8-split"])
 def test_few_replica_dense_against_oracle(n, R, prec, steps):
     """Dense systems beyond one workgroup with R <= 8 (the paper's own runs
     use a single trajectory): the force as R matrix-vector products in the
@@ -217,4 +219,11 @@ def test_dense_path_selection_and_unsupported_shapes():
     assert e.value.status == fth.FTH_EUNSUPPORTED         # matrix-core path needs R in {16..128}
     with pytest.raises(fth.FthError) as e:
         fth.Solver(M, g.A_p, g.C_p, h, replicas=16, precision=fth.FTH_FP32)
-    assert e.value.status == fth.FTH_EUNSUPPORTED
+    assert e.value.status == fth.FTH_EUNSUPPORTED          # plain FP32 beyond one workgroup: R <= 8 only
+    with pytest.raises(fth.FthError) as e:
+        fth.Solver(M, g.A_p, g.C_p, h, precision=fth.FTH_FP32)
+    assert e.value.status == fth.FTH_EUNSUPPORTED          # ... given at create
+    # a context set up for few replicas keeps that form
+    with pytest.raises(fth.FthError) as e:
+        fth.Solver(M, g.A_p, g.C_p, h, replicas=4, precision=fth.FTH_FP64).run(1, replicas=16)
+    assert e.value.status == fth.FTH_ESTATE
