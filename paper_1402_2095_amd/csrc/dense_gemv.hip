@@ -7,9 +7,9 @@
 // Layouts: M row-major Real [N][ld], ld = N rounded up to 4 with zero columns;
 // q_n [ld][R] (the context's q buffers, zero rows past N).  Wave w of workgroup
 // b owns rows ROWS (4 b + w) + (0 .. ROWS-1).  The four waves walk the columns
-// together, 256 per pass: the pass's 256 rows of q_n are staged once in LDS for
-// all four (read from L2 by every wave, they cost more than M itself at R = 8),
-// lane l takes columns 4 l .. 4 l + 3 of the pass, loads 4 entries of each of its
+// together, 256 per pass: from 4 replicas on, the pass's 256 rows of q_n are
+// staged once in LDS for all four (read from L2 by every wave, they cost more
+// than M itself at R = 8); lane l takes columns 4 l .. 4 l + 3 of the pass, loads 4 entries of each of its
 // rows, and keeps one partial sum per (row, replica); the wave then adds the 64
 // lanes' partials in a fixed butterfly, so the result does not depend on
 // scheduling.  The sums are written as the single K slice the dense epilogue
@@ -26,10 +26,14 @@ __global__ __launch_bounds__(256) void dense_gemv_kernel(const DenseGemmArgs g, 
     constexpr int VW = 4;
     constexpr int CH = 64 * VW;          // columns per pass
     constexpr int QV = CH / 4 * R;       // 4-value vectors of q_n per pass
-    __shared__ Vec<Real, 4> qs[2][QV];   // the pass's rows of q_n, double-buffered
+    // From 4 replicas on, q_n read from L2 by every wave costs as much as M itself, so the
+    // pass's rows are staged once in LDS for the four waves; with 1 or 2 replicas each lane
+    // reads its own (fewer bytes than the barrier per pass costs).
+    constexpr bool STAGE = R >= 4;
+    __shared__ Vec<Real, 4> qs[STAGE ? 2 : 1][STAGE ? QV : 1];
     const int tid = threadIdx.x, lane = tid & 63;
     const int64_t row0 = (int64_t(blockIdx.x) * 4 + (tid >> 6)) * ROWS;
-    const bool live = row0 < N;  // a wave past the last row still loads q_n and meets the barriers
+    const bool live = row0 < N;  // a wave past the last row still stages q_n and meets the barriers
     const int64_t n = g.step_base[0] + g.k;
     const Real* __restrict__ q = static_cast<const Real*>((n & 1) ? g.q1 : g.q0);
     Real* part = static_cast<Real*>(g.part);
@@ -42,34 +46,45 @@ __global__ __launch_bounds__(256) void dense_gemv_kernel(const DenseGemmArgs g, 
     for (int rr = 0; rr < ROWS; ++rr)
 #pragma unroll
         for (int r = 0; r < R; ++r) acc[rr][r] = Real(0);
-    // vector x of a pass starting at column j0 holds q_n elements [4x, 4x + 4) of rows
-    // j0 .. j0 + CH - 1, i.e. from row j0 + 4x / R on (ld is a multiple of 4)
-    auto stage = [&](int buf, int64_t j0) {
-        for (int x = tid; x < QV; x += 256)
-            if (j0 + 4 * x / R < ld) qs[buf][x] = load_vec<Real, 4>(q + j0 * R + 4 * x);
+    // ROWS rows' partial sums from columns j .. j+3, with the lane's 4 R values of q_n at qv
+    auto accumulate = [&](int64_t j, const Vec<Real, 4>* qv) {
+        Vec<Real, 4> mv[ROWS];
+#pragma unroll
+        for (int rr = 0; rr < ROWS; ++rr) mv[rr] = load_vec<Real, 4>(mrow[rr] + j);
+#pragma unroll
+        for (int rr = 0; rr < ROWS; ++rr)
+#pragma unroll
+            for (int c = 0; c < VW; ++c)
+#pragma unroll
+                for (int r = 0; r < R; ++r) {
+                    const int e = c * R + r;  // element (j + c, r) of the lane's 4 R values
+                    acc[rr][r] = fmaR(mv[rr].v[c], qv[e >> 2].v[e & 3], acc[rr][r]);
+                }
     };
-    const int64_t npass = (ld + CH - 1) / CH;
-    stage(0, 0);
-    __syncthreads();
-    for (int64_t p = 0; p < npass; ++p) {
-        const int64_t j0 = p * CH, j = j0 + int64_t(lane) * VW;
-        if (p + 1 < npass) stage(int((p + 1) & 1), j0 + CH);  // last read before the previous barrier
-        if (live && j < ld) {
-            const Vec<Real, 4>* qv = &qs[p & 1][lane * R];
-            Vec<Real, 4> mv[ROWS];
-#pragma unroll
-            for (int rr = 0; rr < ROWS; ++rr) mv[rr] = load_vec<Real, 4>(mrow[rr] + j);
-#pragma unroll
-            for (int rr = 0; rr < ROWS; ++rr)
-#pragma unroll
-                for (int c = 0; c < VW; ++c)
-#pragma unroll
-                    for (int r = 0; r < R; ++r) {
-                        const int e = c * R + r;  // element (j + c, r) of the lane's 4 R values
-                        acc[rr][r] = fmaR(mv[rr].v[c], qv[e >> 2].v[e & 3], acc[rr][r]);
-                    }
-        }
+    if constexpr (STAGE) {
+        // vector x of a pass starting at column j0 holds q_n elements [4x, 4x + 4) of rows
+        // j0 .. j0 + CH - 1, i.e. from row j0 + 4x / R on (ld is a multiple of 4)
+        auto stage = [&](int buf, int64_t j0) {
+            for (int x = tid; x < QV; x += 256)
+                if (j0 + 4 * x / R < ld) qs[buf][x] = load_vec<Real, 4>(q + j0 * R + 4 * x);
+        };
+        const int64_t npass = (ld + CH - 1) / CH;
+        stage(0, 0);
         __syncthreads();
+        for (int64_t p = 0; p < npass; ++p) {
+            const int64_t j0 = p * CH, j = j0 + int64_t(lane) * VW;
+            if (p + 1 < npass) stage(int((p + 1) & 1), j0 + CH);  // last read before the previous barrier
+            if (live && j < ld) accumulate(j, &qs[p & 1][lane * R]);
+            __syncthreads();
+        }
+    } else {
+        if (!live) return;
+        for (int64_t j = int64_t(lane) * VW; j < ld; j += CH) {
+            Vec<Real, 4> qv[R];  // q_n rows j .. j+3: 4 R consecutive values
+#pragma unroll
+            for (int u = 0; u < R; ++u) qv[u] = load_vec<Real, 4>(q + j * R + 4 * u);
+            accumulate(j, qv);
+        }
     }
     if (!live) return;
 #pragma unroll
