@@ -86,15 +86,19 @@ def workload(name: str) -> dict:
                  M=M, g=fi.load_gle("fermi_gap_p_ns4"), h=fi.dt_rule(fi.gershgorin_max(M)), R=32,
                  pairs=fi.random_pairs(M.n, 1024, 3004), prec=fth.FTH_FP32, steps=5000,
                  extra=dict(acc_pp=True))
-    elif name in ("dense16384", "dense16384-fp64"):
+    elif name in ("dense16384", "dense16384-fp64", "dense16384-r1"):
+        # -r1: a single trajectory, as the paper runs its examples (the force as a matrix-vector
+        # product in FP32)
         n = 16384
+        R = 1 if name.endswith("r1") else 128
         M = fi.dense_ggt(n, 4004)
         w.update(desc={"workload": "dense SPD N=16384, M = G G^T / N + 0.1 I (FP32 values)",
-                       "gle": "ns=4, x^-1/2 target", "replicas": 128, "estimates": "diagonal + 1024 pairs",
+                       "gle": "ns=4, x^-1/2 target", "replicas": R, "estimates": "diagonal + 1024 pairs",
                        "steps_in_config": 2000},
                  M=M, g=fi.load_gle("invsqrt_ns4"), h=fi.dt_rule(fi.power_lambda_max(M.astype(np.float64), iters=30)),
-                 R=128, pairs=fi.random_pairs(n, 1024, 4005),
-                 prec=fth.FTH_FP64 if name.endswith("fp64") else fth.FTH_FP32_BF16X3, steps=2000)
+                 R=R, pairs=fi.random_pairs(n, 1024, 4005),
+                 prec=(fth.FTH_FP64 if name.endswith("fp64") else fth.FTH_FP32 if name.endswith("r1")
+                       else fth.FTH_FP32_BF16X3), steps=2000)
     elif name == "m1-logdet":
         # the paper's M1 (logarithm example): periodic 24^3 lattice, on-site 100, hopping U[0, 2]
         # to the first six neighbour shells (81 entries per row); log det M = Tr ln M as the
@@ -199,6 +203,12 @@ def unit_of(kernel_name: str):
         gemm, rt, real, ns, rpt, nt = m.groups()
         return "dense", [f"{gemm}<{rt}>", f"dense_epilogue_kernel<{real}, {ns}, {rpt}, "
                                           f"{'true' if nt == '1' else 'false'},"], 1
+    m = re.search(r"dense_gemv_kernel<(\w+),R=(\d+)> \+ dense_epilogue_kernel<(\w+),NS=(\d+),RPT=(\d+),NT=(\d)>",
+                  kernel_name)
+    if m:
+        real, r, _, ns, rpt, nt = m.groups()
+        return "gemv", [f"dense_gemv_kernel<{real}, {r}>", f"dense_epilogue_kernel<{real}, {ns}, {rpt}, "
+                                                          f"{'true' if nt == '1' else 'false'},"], 1
     return None, [], 1
 
 
@@ -284,7 +294,8 @@ def roofline(w: dict, r: dict, steps: int) -> dict:
                              "tb": f"one blocked launch = {r['unit_steps']} steps (step kernel + pair kernel)",
                              "tbp": f"one blocked launch = {r['unit_steps']} steps (persistent step kernel "
                                     "+ pair kernel)",
-                             "dense": "one step (GEMM + epilogue launches)"}.get(r["kind"], "one step"),
+                             "dense": "one step (GEMM + epilogue launches)",
+                             "gemv": "one step (matrix-vector + epilogue launches)"}.get(r["kind"], "one step"),
             "kernels": r["kernels"], "algorithmic_bytes_per_unit": abytes,
             "algorithmic_bytes_per_replica_dof_step": sb / (w["n"] * w["R"]), "avg_unit_us": per_unit_s * 1e6}
     if cnt:
@@ -302,6 +313,8 @@ def roofline(w: dict, r: dict, steps: int) -> dict:
         ws = 2 * (w["g"].ns + 2) * (8 if w["prec"] == fth.FTH_FP64 else 4) * w["n"] * w["R"]
         if ws < CACHE_BYTES:
             roof["cache_resident"] = "working set fits the 256 MB Infinity Cache: effective bandwidth"
+    elif r["kind"] == "gemv":
+        roof["note"] = "few replicas: the force as matrix-vector products with plain FMAs, one pass over M per step"
     else:
         flops = 2.0 * w["n"] * w["n"] * w["R"]
         issued = flops * (3 if w["prec"] == fth.FTH_FP32_BF16X3 else 1)
@@ -331,7 +344,7 @@ def secondary(name: str, steps: int, warmup: int, stream) -> dict:
            "steps": steps, "warmup": warmup,
            "roofline": {k: roof[k] for k in ("bound", "achieved", "peak", "unit", "frac", "avg_unit_us", "traffic")
                         if k in roof}}
-    for k in ("cache_resident", "mfma", "bound_by", "hbm"):
+    for k in ("cache_resident", "mfma", "bound_by", "hbm", "note"):
         if k in roof:
             out["roofline"][k] = roof[k]
     log(f"secondary {name}: {out['ms_per_step'] * 1e3:.1f} us/step")
@@ -736,7 +749,7 @@ def main():
         # warm-ups of about 0.2 s each: the inputs are generated on the host first, and a GPU left
         # idle meanwhile needs that long to return to full clocks
         for name, st, wu in (("banded1e6-fp64", 100, 300), ("banded1e6-pp", 100, 300), ("laplacian64", 1000, 10000),
-                             ("dense16384", 100, 800), ("dense16384-fp64", 50, 200)):
+                             ("dense16384", 100, 800), ("dense16384-fp64", 50, 200), ("dense16384-r1", 100, 800)):
             try:
                 sec[name] = secondary(name, st, wu, stream)
             except Exception as e:  # a secondary workload never hides the headline line
