@@ -23,6 +23,7 @@ def cases():
     band = fi.banded_spd_csr(20011, 5)
     dense, lam = fi.haar_spd(600, 3, 1.0, 50.0)
     small, lam_s = fi.haar_spd(80, 4, 1.0, 50.0)
+    few, lam_f = fi.haar_spd(1100, 6, 1.0, 50.0)
     return [
         ("coded", lap, g, fi.dt_rule(fi.laplacian3d_lambda_max(10, 0.1)),
          dict(replicas=8, acc_pp=True, acc_trace=True)),
@@ -32,6 +33,8 @@ def cases():
          dict(replicas=32, precision=fth.FTH_FP32_BF16X3, acc_trace=True)),
         ("small", small, fi.GLE(4, 3.0 * g.A_p, 3.0 * g.C_p), fi.dt_rule(lam_s.max()),
          dict(replicas=16, precision=fth.FTH_FP64, acc_pp=True, acc_trace=True)),
+        ("dense-few", few, fi.GLE(4, 3.0 * g.A_p, 3.0 * g.C_p), fi.dt_rule(lam_f.max()),
+         dict(replicas=8, precision=fth.FTH_FP64, acc_pp=True, acc_trace=True)),
     ]
 
 
@@ -118,6 +121,16 @@ def test_footprint_matches_held_memory():
     held = plain.device_bytes
     print(f"[footprint] predicted {fp} bytes, held {held} bytes", flush=True)
     assert abs(fp - held) <= 1024
+    # the few-replica dense form (matrix-vector force)
+    D = fi.dense_ggt(5001, 7)
+    dpairs = fi.random_pairs(5001, 64, 2)
+    few = fth.Solver(D, g.A_p, g.C_p, fi.dt_rule(fi.power_lambda_max(D.astype(np.float64))), pairs=dpairs, replicas=4,
+                     precision=fth.FTH_FP32, seed=4, acc_diag=True).run(3)
+    fp = fth.fth_footprint_bytes(D, 4, 4, len(dpairs), True, fth.FTH_FP32)
+    held = few.device_bytes
+    print(f"[footprint] dense 5001, R = 4: predicted {fp} bytes, held {held} bytes ({few.kernel_name})", flush=True)
+    assert "dense_gemv_kernel" in few.kernel_name
+    assert abs(fp - held) <= 4096
 
 
 # PyTorch brings its own HIP runtime; it must be initialised before the
