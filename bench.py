@@ -48,6 +48,7 @@ KERNEL_SOURCES = {
     "tb": ["tb_step.hpp", "tb_step.hip", "row_update.hpp", "noise.hpp"],
     "tbp": ["tbp_step.hpp", "tbp_step.hip", "tb_step.hpp", "row_update.hpp", "noise.hpp"],
     "dense": ["dense.hpp", "dense_f32.hip", "dense_f64.hip", "row_update.hpp", "noise.hpp"],
+    "gemv": ["dense_gemv.hip", "dense.hpp", "dense_f32.hip", "row_update.hpp", "noise.hpp"],
 }
 
 
