@@ -137,7 +137,8 @@ def normwise(a, b):
 
 def test_mix_against_oracle():
     """One server running sparse FP32 requests of uneven size (packed), a
-    dense split-BF16x3 request and a sparse FP64 request side by side for
+    dense split-BF16x3 request, a dense request of 8 replicas (matrix-vector
+    force) and a sparse FP64 request side by side for
     1000 steps: each request's estimates and block stderrs equal the FP64
     oracle's for the same inputs, seed and noise stream, to the FP32 (1e-4)
     or FP64 (1e-10) trajectory tolerance."""
@@ -147,6 +148,7 @@ def test_mix_against_oracle():
             ("lap12", lap_request(12, 62, 32), fth.FTH_FP32, 32),
             ("band5003", band_request(5003, 63, 33), fth.FTH_FP32, 32),
             ("dense600", dense_request(600, 64, 34), fth.FTH_FP32_BF16X3, 64),
+            ("dense1100-r8", dense_request(1100, 66, 36), fth.FTH_FP32_BF16X3, 8),   # matrix-vector form
             ("band3001-fp64", dict(band_request(3001, 65, 35), precision=fth.FTH_FP64), fth.FTH_FP64, 8)]
     srv = fth.Server(steps_per_tick=100)
     ids = []
