@@ -22,7 +22,7 @@ namespace dev {
 template <typename Real, int R>
 __global__ __launch_bounds__(256) void dense_gemv_kernel(const DenseGemmArgs g, const Real* __restrict__ M, int64_t N,
                                                          int64_t ld) {
-    constexpr int ROWS = (sizeof(Real) == 8 && R == 8) ? 4 : 8;
+    constexpr int ROWS = 8;
     constexpr int VW = 4;
     constexpr int CH = 64 * VW;          // columns per pass
     constexpr int QV = CH / 4 * R;       // 4-value vectors of q_n per pass
@@ -100,7 +100,7 @@ __global__ __launch_bounds__(256) void dense_gemv_kernel(const DenseGemmArgs g, 
 
 template <typename Real, int R>
 int launch_gemv_r(const DenseGemmArgs& g, const Real* M, int64_t N, int64_t ld, void* stream) {
-    constexpr int ROWS = (sizeof(Real) == 8 && R == 8) ? 4 : 8;
+    constexpr int ROWS = 8;
     const int64_t waves = (N + ROWS - 1) / ROWS;
     const int64_t grid = (waves + 3) / 4;
     if (grid > 0x7FFFFFFF) return -3;
