@@ -345,7 +345,7 @@ def secondary(name: str, steps: int, warmup: int, stream) -> dict:
            "steps": steps, "warmup": warmup,
            "roofline": {k: roof[k] for k in ("bound", "achieved", "peak", "unit", "frac", "avg_unit_us", "traffic")
                         if k in roof}}
-    for k in ("cache_resident", "mfma", "bound_by", "hbm", "note"):
+    for k in ("cache_resident", "mfma", "bound_by", "hbm", "note", "valu"):
         if k in roof:
             out["roofline"][k] = roof[k]
     log(f"secondary {name}: {out['ms_per_step'] * 1e3:.1f} us/step")
