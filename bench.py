@@ -310,6 +310,8 @@ def roofline(w: dict, r: dict, steps: int) -> dict:
                         "bytes and is VALU-bound (valu_busy from SQ_ACTIVE_INST_VALU)")
         roof["valu"] = {"busy_frac_counter": cnt.get("valu_busy"), "insts_per_unit_counter": cnt.get("valu_insts_per_unit"),
                         "model_ops_per_unit": alu_ops, "model_frac": alu_ops / per_unit_s / 1e9 / ALU_PEAK_GOPS}
+    elif cnt.get("valu_busy") is not None:
+        roof["valu"] = {"busy_frac_counter": cnt["valu_busy"], "insts_per_unit_counter": cnt.get("valu_insts_per_unit")}
     if not w["dense"]:
         ws = 2 * (w["g"].ns + 2) * (8 if w["prec"] == fth.FTH_FP64 else 4) * w["n"] * w["R"]
         if ws < CACHE_BYTES:
