@@ -83,9 +83,11 @@ def test_dense_trajectory_parity(prec):
                                              (2100, 4, fth.FTH_FP32, (1, 10, 100, 1000)),
                                              (4500, 1, fth.FTH_FP32, (1, 10, 100, 1000)),
                                              (1100, 8, fth.FTH_FP64, (1, 10, 100, 1000)),
-                                             (5003, 8, fth.FTH_FP32_BF16X3, (1, 10, 100))],
+                                             (5003, 8, fth.FTH_FP32_BF16X3, (1, 10, 100)),
+                                             (4097, 1, fth.FTH_FP64, (1, 10, 100)),
+                                             (2049, 2, fth.FTH_FP32, (1, 10, 100))],
                          ids=["4200-R1-fp64", "4200-R2-split", "2100-R4-fp32", "4500-R1-fp32", "1100-R8-fp64",
-                              "5003-R8-split"])
+                              "5003-R8-split", "4097-R1-fp64", "2049-R2-fp32"])
 def test_few_replica_dense_against_oracle(n, R, prec, steps):
     """Dense systems beyond one workgroup with R <= 8 (the paper's own runs
     use a single trajectory): the force as R matrix-vector products in the
